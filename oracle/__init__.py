@@ -1,0 +1,148 @@
+"""FP64 oracle for the hyper-systolic matrix product -- TEST INFRASTRUCTURE.
+
+Only the test-suite, the smoke check and the benchmark's CPU-baseline leg
+may import this package.  The product path (the HIP library and its Python
+binding) never touches it, and the two share no code.
+
+What it computes is the plain definition the method reaches exactly
+(Sec. 3.1, Eq. PRODUCT): c_ij = sum_k a_ik b_kj in double precision, ascending
+k, plus the transposed product, the matrix-vector product and the gradient of
+L = sum(C * G).  See ``hs_oracle.c``.  ``ring`` holds a literal simulator of
+Algorithms SYSTOLIC and HYPER-SYSTOLIC (Sec. 5) and ``bases`` the regular
+hyper-systolic bases (Sec. 4.4, Sec. 5.2.1); both pin the schedule.
+
+Parity pins: see tests/test_oracle.py (identity, permutation, small-integer
+exactness, explicit transpose, associativity, central differences, exactly
+rounded brute force).
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        path = _build.build(force=False)
+        lib = ctypes.CDLL(path)
+        i64 = ctypes.c_int64
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int64)
+        lib.hs_oracle_gemm.argtypes = [i64, i64, i64, dp, i64, dp, i64, dp, i64]
+        lib.hs_oracle_gemm_tn.argtypes = [i64, i64, i64, dp, i64, dp, i64, dp, i64]
+        lib.hs_oracle_gemv.argtypes = [i64, i64, dp, i64, dp, dp]
+        lib.hs_oracle_backward.argtypes = [i64, i64, i64, dp, i64, dp, i64, dp, i64,
+                                           dp, i64, dp, i64]
+        lib.hs_oracle_gemm_rows.argtypes = [i64, i64, dp, i64, dp, i64, ip, i64, dp, i64]
+        lib.hs_oracle_gemm_tn_rows.argtypes = [i64, i64, dp, i64, dp, i64, ip, i64, dp, i64]
+        lib.hs_oracle_grad_a_rows.argtypes = [i64, i64, dp, i64, dp, i64, ip, i64, dp, i64]
+        for f in ("hs_oracle_gemm", "hs_oracle_gemm_tn", "hs_oracle_gemv",
+                  "hs_oracle_backward", "hs_oracle_gemm_rows", "hs_oracle_gemm_tn_rows",
+                  "hs_oracle_grad_a_rows"):
+            getattr(lib, f).restype = None
+        _lib = lib
+    return _lib
+
+
+def _d(x):
+    """Promote to a C-contiguous float64 array (the stored values, exactly)."""
+    return np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def gemm(A, B):
+    """C = A . B  (A m x k, B k x n), Eq. PRODUCT."""
+    A, B = _d(A), _d(B)
+    m, k = A.shape
+    k2, n = B.shape
+    assert k == k2
+    C = np.empty((m, n), np.float64)
+    _load().hs_oracle_gemm(m, n, k, _p(A), k, _p(B), n, _p(C), n)
+    return C
+
+
+def gemm_tn(A, B):
+    """C = A^T . B with A stored k x m (transposed product of the abstract)."""
+    A, B = _d(A), _d(B)
+    k, m = A.shape
+    k2, n = B.shape
+    assert k == k2
+    C = np.empty((m, n), np.float64)
+    _load().hs_oracle_gemm_tn(m, n, k, _p(A), m, _p(B), n, _p(C), n)
+    return C
+
+
+def gemv(A, x):
+    """y = A . x (matrix-vector product of the abstract)."""
+    A, x = _d(A), _d(x)
+    m, n = A.shape
+    assert x.shape == (n,)
+    y = np.empty(m, np.float64)
+    _load().hs_oracle_gemv(m, n, _p(A), n, _p(x), _p(y))
+    return y
+
+
+def backward(A, B, G, need_a=True, need_b=True):
+    """Gradient of L = sum(C * G), C = A . B:  dA = G . B^T, dB = A^T . G."""
+    A, B, G = _d(A), _d(B), _d(G)
+    m, k = A.shape
+    k2, n = B.shape
+    assert k == k2 and G.shape == (m, n)
+    dA = np.empty((m, k), np.float64) if need_a else None
+    dB = np.empty((k, n), np.float64) if need_b else None
+    null = ctypes.POINTER(ctypes.c_double)()
+    _load().hs_oracle_backward(m, n, k, _p(A), k, _p(B), n, _p(G), n,
+                               _p(dA) if need_a else null, k,
+                               _p(dB) if need_b else null, n)
+    return dA, dB
+
+
+def _rows(rows):
+    r = np.ascontiguousarray(np.asarray(rows, dtype=np.int64))
+    return r, r.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+
+
+def gemm_rows(A, B, rows):
+    """Rows ``rows`` of A . B (for sizes where the full product is too slow)."""
+    A, B = _d(A), _d(B)
+    m, k = A.shape
+    n = B.shape[1]
+    r, rp = _rows(rows)
+    out = np.empty((len(r), n), np.float64)
+    _load().hs_oracle_gemm_rows(n, k, _p(A), k, _p(B), n, rp, len(r), _p(out), n)
+    return out
+
+
+def gemm_tn_rows(A, B, rows):
+    """Rows ``rows`` of A^T . B with A stored k x m."""
+    A, B = _d(A), _d(B)
+    k, m = A.shape
+    n = B.shape[1]
+    r, rp = _rows(rows)
+    out = np.empty((len(r), n), np.float64)
+    _load().hs_oracle_gemm_tn_rows(n, k, _p(A), m, _p(B), n, rp, len(r), _p(out), n)
+    return out
+
+
+def grad_a_rows(G, B, rows):
+    """Rows ``rows`` of dA = G . B^T (G m x n, B k x n)."""
+    G, B = _d(G), _d(B)
+    m, n = G.shape
+    k = B.shape[0]
+    r, rp = _rows(rows)
+    out = np.empty((len(r), k), np.float64)
+    _load().hs_oracle_grad_a_rows(n, k, _p(G), n, _p(B), n, rp, len(r), _p(out), k)
+    return out
+
+
+def grad_b_rows(A, G, rows):
+    """Rows ``rows`` of dB = A^T . G (A m x k, G m x n)."""
+    return gemm_tn_rows(A, G, rows)

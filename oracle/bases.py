@@ -1,0 +1,47 @@
+"""Hyper-systolic bases (Sec. 4.2-4.4 and Sec. 5.2.1).
+
+TEST INFRASTRUCTURE ONLY.  Written from the definitions; used to pin the
+library's schedule generator and the counting theorems.
+"""
+
+
+def regular_bases_two_array(n, K):
+    """Def. REGULARBASE2: A=(0,1,..,1) with K-1 ones, B=(0,K,..,K) with K~-1 K's."""
+    assert n % K == 0
+    Kt = n // K
+    return [0] + [1] * (K - 1), [0] + [K] * (Kt - 1)
+
+
+def matrix_product_bases(p, K):
+    """Sec. 5.2.1: A=(0,K,..,K) (K~-1 entries), B=(0,-1,..,-1), C=(0,1,..,1) (K-1)."""
+    assert p % K == 0
+    Kt = p // K
+    return [0] + [K] * (Kt - 1), [0] + [-1] * (K - 1), [0] + [1] * (K - 1)
+
+
+def ordered_partial_sums(base):
+    """All sums a_i + ... + a_{i+j} over contiguous runs of the base (Eq. ADD2)."""
+    s = set()
+    for i in range(len(base)):
+        acc = 0
+        for j in range(i, len(base)):
+            acc += base[j]
+            s.add(acc)
+    return s
+
+
+def h_range_complete(A, B, n):
+    """True iff every m in 0..n-1 is a sum of two ordered partial sums (Def. DEF:OPTI2)."""
+    sa, sb = ordered_partial_sums(A), ordered_partial_sums(B)
+    reach = {x + y for x in sa for y in sb}
+    return all(m in reach for m in range(n))
+
+
+def shifts_two_array(K, Kt):
+    """Thm. GAIN2, Eq. COMPLEXR: (K-1) + (K~-1) forward shifts, (K-1) back-shifts."""
+    return 2 * K + Kt - 3
+
+
+def shifts_matrix_product(K, Kt):
+    """Thm. GAIN3, Eq. COMPL: 1 pre-shift of B, K~-1 shifts of A, K-1 of C."""
+    return K + Kt - 1

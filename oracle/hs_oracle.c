@@ -1,0 +1,172 @@
+/*
+ * hs_oracle.c -- FP64 reference for the hyper-systolic matrix product.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing on the product path may include, link
+ * or call this file; only the test-suite, the smoke check and the CPU
+ * baseline leg of the benchmark use it.  It shares no code, header, table
+ * or helper with the HIP library.
+ *
+ * The hyper-systolic method reorders communication but computes exactly the
+ * ordinary matrix product (Sec. 3.1, Eq. PRODUCT: c_ij = sum_k a_ik b_kj;
+ * Sec. 5.2.3, Thm. GAIN3 -- no extra or fewer multiply-adds).  The oracle is
+ * therefore that definition written out: plain triple loops in double
+ * precision, contraction index ascending, no blocking, no reordering.
+ * OpenMP splits independent output rows only; every output element is one
+ * sequential ascending-k sum, so the result does not depend on thread count.
+ *
+ * All matrices are dense, row-major, with explicit leading dimensions
+ * (elements between consecutive rows).  Inputs are the stored values of the
+ * caller's matrices promoted to double.
+ */
+#include <stdint.h>
+#include <stddef.h>
+
+/* C[m,n] = A[m,k] . B[k,n]  (Eq. PRODUCT, with A n x m and B m x n
+ * generalised to rectangular M x Kd times Kd x N). */
+void hs_oracle_gemm(int64_t m, int64_t n, int64_t k,
+                    const double *A, int64_t lda,
+                    const double *B, int64_t ldb,
+                    double *C, int64_t ldc)
+{
+    int64_t i;
+#pragma omp parallel for schedule(static)
+    for (i = 0; i < m; ++i) {
+        for (int64_t j = 0; j < n; ++j) {
+            double s = 0.0;
+            for (int64_t p = 0; p < k; ++p)
+                s += A[i * lda + p] * B[p * ldb + j];
+            C[i * ldc + j] = s;
+        }
+    }
+}
+
+/* C[m,n] = A^T . B with A stored as a k x m matrix (the transposed product
+ * the paper announces in its abstract and summary): c_ij = sum_p a_pi b_pj. */
+void hs_oracle_gemm_tn(int64_t m, int64_t n, int64_t k,
+                       const double *A, int64_t lda,
+                       const double *B, int64_t ldb,
+                       double *C, int64_t ldc)
+{
+    int64_t i;
+#pragma omp parallel for schedule(static)
+    for (i = 0; i < m; ++i) {
+        for (int64_t j = 0; j < n; ++j) {
+            double s = 0.0;
+            for (int64_t p = 0; p < k; ++p)
+                s += A[p * lda + i] * B[p * ldb + j];
+            C[i * ldc + j] = s;
+        }
+    }
+}
+
+/* y[m] = A[m,n] . x[n]  (the matrix-vector product of the abstract). */
+void hs_oracle_gemv(int64_t m, int64_t n,
+                    const double *A, int64_t lda,
+                    const double *x, double *y)
+{
+    int64_t i;
+#pragma omp parallel for schedule(static)
+    for (i = 0; i < m; ++i) {
+        double s = 0.0;
+        for (int64_t j = 0; j < n; ++j)
+            s += A[i * lda + j] * x[j];
+        y[i] = s;
+    }
+}
+
+/* Gradient of L = sum_ij C_ij G_ij with C = A B (A m x k, B k x n, G m x n):
+ *   dL/da_ip = sum_j g_ij b_pj   (dA = G . B^T, m x k)
+ *   dL/db_pj = sum_i a_ip g_ij   (dB = A^T . G, k x n)
+ * Either output pointer may be NULL to skip it. */
+void hs_oracle_backward(int64_t m, int64_t n, int64_t k,
+                        const double *A, int64_t lda,
+                        const double *B, int64_t ldb,
+                        const double *G, int64_t ldg,
+                        double *dA, int64_t ldda,
+                        double *dB, int64_t lddb)
+{
+    int64_t i;
+    if (dA) {
+#pragma omp parallel for schedule(static)
+        for (i = 0; i < m; ++i) {
+            for (int64_t p = 0; p < k; ++p) {
+                double s = 0.0;
+                for (int64_t j = 0; j < n; ++j)
+                    s += G[i * ldg + j] * B[p * ldb + j];
+                dA[i * ldda + p] = s;
+            }
+        }
+    }
+    if (dB) {
+#pragma omp parallel for schedule(static)
+        for (i = 0; i < k; ++i) {
+            for (int64_t j = 0; j < n; ++j) {
+                double s = 0.0;
+                for (int64_t q = 0; q < m; ++q)
+                    s += A[q * lda + i] * G[q * ldg + j];
+                dB[i * lddb + j] = s;
+            }
+        }
+    }
+}
+
+/* Selected rows of C = A . B: out[t, :] = row rows[t] of the product.
+ * Used where the full product is too large for the CPU (sampled-row parity). */
+void hs_oracle_gemm_rows(int64_t n, int64_t k,
+                         const double *A, int64_t lda,
+                         const double *B, int64_t ldb,
+                         const int64_t *rows, int64_t nrows,
+                         double *out, int64_t ldo)
+{
+    int64_t t;
+#pragma omp parallel for schedule(static)
+    for (t = 0; t < nrows; ++t) {
+        const int64_t i = rows[t];
+        for (int64_t j = 0; j < n; ++j) {
+            double s = 0.0;
+            for (int64_t p = 0; p < k; ++p)
+                s += A[i * lda + p] * B[p * ldb + j];
+            out[t * ldo + j] = s;
+        }
+    }
+}
+
+/* Selected rows of C = A^T . B (A stored k x m). */
+void hs_oracle_gemm_tn_rows(int64_t n, int64_t k,
+                            const double *A, int64_t lda,
+                            const double *B, int64_t ldb,
+                            const int64_t *rows, int64_t nrows,
+                            double *out, int64_t ldo)
+{
+    int64_t t;
+#pragma omp parallel for schedule(static)
+    for (t = 0; t < nrows; ++t) {
+        const int64_t i = rows[t];
+        for (int64_t j = 0; j < n; ++j) {
+            double s = 0.0;
+            for (int64_t p = 0; p < k; ++p)
+                s += A[p * lda + i] * B[p * ldb + j];
+            out[t * ldo + j] = s;
+        }
+    }
+}
+
+/* Selected rows of dA = G . B^T (row i: sum_j g_ij b_pj). */
+void hs_oracle_grad_a_rows(int64_t n, int64_t k,
+                           const double *G, int64_t ldg,
+                           const double *B, int64_t ldb,
+                           const int64_t *rows, int64_t nrows,
+                           double *out, int64_t ldo)
+{
+    int64_t t;
+#pragma omp parallel for schedule(static)
+    for (t = 0; t < nrows; ++t) {
+        const int64_t i = rows[t];
+        for (int64_t p = 0; p < k; ++p) {
+            double s = 0.0;
+            for (int64_t j = 0; j < n; ++j)
+                s += G[i * ldg + j] * B[p * ldb + j];
+            out[t * ldo + p] = s;
+        }
+    }
+}

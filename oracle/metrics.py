@@ -1,0 +1,27 @@
+"""Error metrics against the FP64 oracle (test infrastructure).
+
+err_row  = max_r ||C_r - Chat_r||_2 / ||Chat_r||_2
+           (relative error per output row; insensitive to per-row scales)
+err_elem = max_ij |C_ij - Chat_ij| / (|A| |B|)_ij
+           (error relative to the sum of absolute products, the natural
+           scale of a rounding error in a dot product)
+"""
+import numpy as np
+
+
+def err_row(C, ref):
+    C = np.asarray(C, np.float64)
+    ref = np.asarray(ref, np.float64)
+    if C.ndim == 1:
+        C, ref = C[None, :], ref[None, :]
+    num = np.linalg.norm(C - ref, axis=1)
+    den = np.linalg.norm(ref, axis=1)
+    den = np.where(den == 0, 1.0, den)
+    return float(np.max(num / den)) if C.size else 0.0
+
+
+def err_elem(C, ref, absprod):
+    C = np.asarray(C, np.float64)
+    ref = np.asarray(ref, np.float64)
+    den = np.where(absprod == 0, 1.0, absprod)
+    return float(np.max(np.abs(C - ref) / den)) if C.size else 0.0
