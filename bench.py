@@ -1,0 +1,154 @@
+"""Benchmark: hyper-systolic product forward + backward at n = 8192 on one GPU.
+
+One step = the whole hot path over one batch of synthetic input:
+C = A . B, dA = G . B^T, dB = A^T . G (three products on the schedule
+(p, K)), each with its operand preparation, main MFMA loop and back-shift.
+Inputs: A, B ~ N(0, 1) rows scaled log-uniformly in [1e-3, 1e3],
+G ~ N(0, 1), seeded, resident in HBM before the timed region.
+
+Prints ONE JSON line.  ``value`` is the useful TFLOP/s of the split-BF16
+form (3 * 2 n^3 flops per step over the timed wall clock); the plain FP32
+form of the same step is measured beside it under ``comparison``.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {  # MI355X published dense peaks
+    "bf16": 2516.6, "f16": 2516.6, "fp8": 5033.2, "f32": 157.3, "f64": 78.6, "hbm_gbs": 8000.0,
+}
+MFMA_PRODUCTS = {"split3_bf16": 6, "bf16": 1, "f16": 1, "f32": 1, "f64": 1}
+MFMA_PEAK_KEY = {"split3_bf16": "bf16", "bf16": "bf16", "f16": "f16", "f32": "f32", "f64": "f64"}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=8192)
+    ap.add_argument("--p", type=int, default=64)
+    ap.add_argument("--K", type=int, default=2)
+    ap.add_argument("--form", default="split3_bf16")
+    ap.add_argument("--compare", default="f32", help="form timed beside the headline ('' to skip)")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target CPU time of the oracle baseline sample (0 to skip)")
+    return ap.parse_args()
+
+
+def step(hs, A, B, G, form, p, K):
+    C = hs.hs_gemm(A, B, dtype=form, p=p, K=K)
+    dA, dB = hs.hs_gemm_backward(A, B, G, dtype=form, p=p, K=K)
+    return C, dA, dB
+
+
+def run_form(hs, torch, A, B, G, form, p, K, steps, warmup):
+    for _ in range(warmup):
+        step(hs, A, B, G, form, p, K)
+    torch.cuda.synchronize()
+    hs.hs_profile_begin()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step(hs, A, B, G, form, p, K)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern_ms, launches = hs.hs_profile_end()
+    return wall, kern_ms, launches
+
+
+def cpu_baseline(A64, B64, G64, target_s):
+    """The FP64 oracle on sampled rows of C, dA and dB (bounded sample)."""
+    import oracle
+    from paper_cs_9809105_amd import inputs
+    n = A64.shape[0]
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    # calibrate on 2 rows of each product, then size the sample to ~target_s
+    rows = inputs.sample_rows(n, 2, seed=7)
+    t0 = time.perf_counter()
+    oracle.gemm_rows(A64, B64, rows)
+    oracle.grad_a_rows(G64, B64, rows)
+    oracle.grad_b_rows(A64, G64, rows)
+    t_cal = time.perf_counter() - t0
+    nrows = max(2, min(n, int(2 * target_s / max(t_cal, 1e-6))))
+    nrows = max(cores, (nrows // cores) * cores) if nrows >= cores else nrows
+    rows = inputs.sample_rows(n, nrows, seed=8)
+    t0 = time.perf_counter()
+    oracle.gemm_rows(A64, B64, rows)
+    oracle.grad_a_rows(G64, B64, rows)
+    oracle.grad_b_rows(A64, G64, rows)
+    dt = time.perf_counter() - t0
+    flops = 3 * 2.0 * nrows * n * n
+    return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
+            "sample": "%d of %d rows of each of C, dA, dB (n=%d, FP64 triple loop, %.1f s)"
+                      % (nrows, n, n, dt)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the build runs on a single MI355X "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import paper_cs_9809105_amd as hs
+    from paper_cs_9809105_amd import inputs
+
+    n, p, K = args.n, args.p, args.K
+    A64 = inputs.row_scaled((n, n), seed=inputs.BASE_SEED + 2)
+    B64 = inputs.row_scaled((n, n), seed=inputs.BASE_SEED + 3)
+    G64 = inputs.normal((n, n), seed=inputs.BASE_SEED + 4)
+    A = torch.from_numpy(A64).float().cuda()
+    B = torch.from_numpy(B64).float().cuda()
+    G = torch.from_numpy(G64).float().cuda()
+    # the oracle sees exactly the stored fp32 values
+    A64 = A.cpu().double().numpy()
+    B64 = B.cpu().double().numpy()
+    G64 = G.cpu().double().numpy()
+    torch.cuda.synchronize()
+
+    useful = 3 * 2.0 * n ** 3
+    wall, kern_ms, launches = run_form(hs, torch, A, B, G, args.form, p, K, args.steps, args.warmup)
+    ms_step = wall * 1e3 / args.steps
+    value = useful * args.steps / wall / 1e12
+    avg_kernel_ms = kern_ms / max(launches, 1)
+    mfma_flops = MFMA_PRODUCTS[args.form] * 2.0 * n ** 3      # per main-kernel launch
+    achieved = mfma_flops / (avg_kernel_ms * 1e-3) / 1e12
+    peak = PEAK[MFMA_PEAK_KEY[args.form]]
+
+    comparison = None
+    if args.compare:
+        w2, k2, l2 = run_form(hs, torch, A, B, G, args.compare, p, K, max(2, args.steps // 2), 1)
+        s2 = max(2, args.steps // 2)
+        comparison = {args.compare: {"value": useful * s2 / w2 / 1e12, "ms_per_step": w2 * 1e3 / s2,
+                                     "avg_main_kernel_ms": k2 / max(l2, 1)}}
+
+    cpu = None
+    if args.cpu_seconds > 0:
+        cpu = cpu_baseline(A64, B64, G64, args.cpu_seconds)
+
+    out = {
+        "metric": "TFLOP/s at n=8192: split-BF16 (FP32-accurate) vs plain FP32 GEMM; fwd+bwd",
+        "value": value, "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16x3" if args.form == "split3_bf16" else args.form, "data": "synthetic",
+        "config": {"workload": "hyper-systolic C=A.B + dA=G.B^T + dB=A^T.G, square n=%d, "
+                               "row-scaled N(0,1) A and B, N(0,1) G" % n,
+                   "n": n, "p": p, "K": K, "form": args.form},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None,
+                     "kernel": "mm_kernel (main MFMA loop)", "avg_kernel_ms": avg_kernel_ms,
+                     "launches": launches},
+        "comparison": comparison,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,182 @@
+/*
+ * hs.h -- hyper-systolic matrix products on AMD MI355X (gfx950): C ABI.
+ *
+ * The method (Lippert, Petkov, Palazzari, Schilling, "Hyper-Systolic Matrix
+ * Multiplication", Sec. 5, Algorithm HYPER-SYSTOLIC) computes the ordinary
+ * product c_ij = sum_k a_ik b_kj (Sec. 3.1, Eq. PRODUCT) on a ring of p
+ * processors with K * K~ = p.  Here the p processors are virtual: groups of
+ * workgroups on one GPU.  Virtual processor v owns row stripe v of A and C;
+ * the row stripes of B travel.  With 0-based indices:
+ *
+ *   step j = 0..K~-1 : v holds B stripe kb = (v + j K) mod p
+ *                      (base A = (0, K, .., K), Sec. 5.2.1)
+ *   l = 0..K-1       : c^l_v += A[(v - l) mod p, kb] . B[kb, :]
+ *                      (pre-shift base B = (0, -1, .., -1))
+ *   back-shift       : C[r, :] = c^0_r + (c^1_{r+1} + ( .. + c^{K-1}_{r+K-1}))
+ *                      (base C = (0, 1, .., 1))
+ *
+ * This is Algorithm HYPER-SYSTOLIC applied to C^T = B^T A^T (the paper moves
+ * A and keeps columns; here rows are kept and B moves).  The "cshift" of a
+ * stripe is the order in which its tiles are fetched from HBM into a
+ * double-buffered LDS ring; the K auxiliary arrays C^l are K partial
+ * accumulators; the back-shift is a fixed-order reduction.
+ *
+ * Conventions for every entry point
+ *  - All matrices are dense and row-major; a leading dimension (ld*) is the
+ *    element distance between consecutive rows and must be >= the row length.
+ *  - Every pointer except `ws` and the optional outputs of the backward call
+ *    is a DEVICE pointer owned by the caller.  The library never allocates
+ *    or frees device memory and never synchronises the stream: work is
+ *    enqueued on `stream` (a hipStream_t; NULL means the null stream) and
+ *    completes asynchronously.  Device faults surface at the caller's next
+ *    synchronisation.
+ *  - `ws` is a caller-owned device workspace of at least
+ *    hs_workspace_size(...) bytes, 256-byte aligned (NULL allowed when that
+ *    size is 0).  Its contents on return are unspecified; two calls that
+ *    overlap in time must not share one workspace.
+ *  - All argument checks (shapes, schedule, pointers, alignment, dtype,
+ *    workspace size) run on the host before any launch; on failure nothing
+ *    is enqueued and a non-zero hs_status is returned.  The library never
+ *    aborts the process.  A launch error reported by the runtime is returned
+ *    as HS_ERR_LAUNCH_FAILED.
+ *  - The schedule: 1 <= p <= 4096, K divides p (K = 0 selects the divisor of
+ *    p that minimises the shift count K + p/K - 1, i.e. K = sqrt(p) when p
+ *    is a perfect square; Sec. 4.4, Thm. on minimal length).  Stripes are
+ *    ceil(rows / p) high; a ragged last stripe and contraction blocks are
+ *    padded with zeros, which does not change the product.
+ *  - Results are deterministic: the schedule and every summation order are
+ *    fixed, so the same inputs give the same bits on every run.
+ */
+#ifndef HS_H
+#define HS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Arithmetic forms.  "in" is the storage type of A, B (and G, x); "out" that
+ * of C (and dA, dB, y).
+ *  HS_F64          in f64,  out f64.  FP64 MFMA (v_mfma_f64_16x16x4).
+ *  HS_F32          in f32,  out f32.  FP32 MFMA (v_mfma_f32_32x32x2).
+ *  HS_BF16         in bf16, out f32.  BF16 MFMA, FP32 accumulation.
+ *  HS_F16          in f16,  out f32.  FP16 MFMA, FP32 accumulation.
+ *  HS_SPLIT3_BF16  in f32,  out f32.  a = a0 + a1 + a2 with bf16 pieces
+ *                  (round-to-nearest-even, exact residuals); the six products
+ *                  a_i b_j with i + j <= 2 on BF16 MFMA, FP32 accumulation,
+ *                  partial results summed in FP64.
+ *  HS_FP8_E4M3     in f32,  out f32.  a ~= q0 / s with q0 = e4m3(a s) and a
+ *                  power-of-two s per 128 x 128 tile of the operand; one
+ *                  FP8 MFMA product with hardware block scales.
+ *  HS_FP8_E4M3_R1  in f32,  out f32.  One refinement step: a ~= (q0 + q1/s1)/s
+ *                  with q1 = e4m3((a s - q0) s1), s1 a power of two per tile;
+ *                  products q0 q0', q0 q1', q1 q0'. */
+typedef enum {
+    HS_F64 = 0,
+    HS_F32 = 1,
+    HS_BF16 = 2,
+    HS_F16 = 3,
+    HS_SPLIT3_BF16 = 4,
+    HS_FP8_E4M3 = 5,
+    HS_FP8_E4M3_R1 = 6
+} hs_dtype;
+
+typedef enum {
+    HS_OK = 0,
+    HS_ERR_INVALID_VALUE = 1,       /* bad shape, ld, pointer, schedule */
+    HS_ERR_NOT_SUPPORTED = 2,       /* dtype not available for this call */
+    HS_ERR_WORKSPACE_TOO_SMALL = 3, /* ws_bytes < hs_workspace_size(...) */
+    HS_ERR_LAUNCH_FAILED = 4        /* the HIP runtime rejected a launch */
+} hs_status;
+
+/* Which call a workspace is sized for. */
+typedef enum {
+    HS_OP_GEMM = 0,
+    HS_OP_GEMM_TN = 1,
+    HS_OP_GEMV = 2,
+    HS_OP_BACKWARD = 3
+} hs_op;
+
+/* p virtual processors on a logical ring, K * K~ = p (Sec. 5.2).
+ * K == 0 selects the default described above. */
+typedef struct {
+    int32_t p;
+    int32_t K;
+} hs_schedule;
+
+/* Human-readable name of a status code (static string, never NULL). */
+const char *hs_status_string(hs_status s);
+
+/* Resolve K == 0 to its default and validate the schedule.
+ * Host only.  Returns HS_ERR_INVALID_VALUE if p < 1, p > 4096, K < 0 or
+ * K does not divide p. */
+hs_status hs_schedule_resolve(hs_schedule in, hs_schedule *out);
+
+/* The index map of Algorithm HYPER-SYSTOLIC in row orientation (host only,
+ * for inspection and tests).  Writes, for v = 0..p-1, j = 0..K~-1,
+ * l = 0..K-1 in that nesting order, the pair (r, kb): output stripe
+ * r = (v - l) mod p and contraction block kb = (v + j K) mod p, into out[]
+ * (2 * p * K~ * K = 2 p^2 int32 values).  Returns HS_ERR_INVALID_VALUE if
+ * cap (in int32 elements) is too small or the schedule is invalid. */
+hs_status hs_schedule_table(hs_schedule s, int32_t *out, size_t cap);
+
+/* Bytes of device workspace that `op` needs for these sizes (m, n, k as in
+ * the corresponding call; for HS_OP_GEMV k is ignored).  Returns 0 if none
+ * is needed, and SIZE_MAX if the arguments are invalid. */
+size_t hs_workspace_size(hs_op op, int64_t m, int64_t n, int64_t k,
+                         hs_dtype dtype, hs_schedule s);
+
+/* C[m, n] = A[m, k] . B[k, n]  (Eq. PRODUCT; Algorithm HYPER-SYSTOLIC).
+ * A: m x k, lda >= k.  B: k x n, ldb >= n.  C: m x n, ldc >= n (written,
+ * never read).  All dtypes.  m, n or k may be 0 (k == 0 writes zeros). */
+hs_status hs_gemm(int64_t m, int64_t n, int64_t k, hs_dtype dtype, hs_schedule s,
+                  const void *A, int64_t lda, const void *B, int64_t ldb,
+                  void *C, int64_t ldc, void *ws, size_t ws_bytes, void *stream);
+
+/* C[m, n] = A^T . B with A stored k x m (lda >= m), B k x n (ldb >= n).
+ * The transposed product the paper says runs "on the same footing" (Abstract,
+ * Sec. 8): the same schedule, with A's tiles read along its columns.
+ * All dtypes. */
+hs_status hs_gemm_tn(int64_t m, int64_t n, int64_t k, hs_dtype dtype, hs_schedule s,
+                     const void *A, int64_t lda, const void *B, int64_t ldb,
+                     void *C, int64_t ldc, void *ws, size_t ws_bytes, void *stream);
+
+/* y[m] = A[m, n] . x[n]  (the matrix-vector product of the Abstract and
+ * Sec. 8).  Virtual processor v owns row stripe v of A and y; x stripes
+ * travel in the order of base A; the K partial vectors are combined in the
+ * back-shift order, in FP64 for HS_F32.  dtype: HS_F32 or HS_F64.  lda >= n.
+ * Needs no workspace (ws may be NULL). */
+hs_status hs_gemv(int64_t m, int64_t n, hs_dtype dtype, hs_schedule s,
+                  const void *A, int64_t lda, const void *x, void *y,
+                  void *ws, size_t ws_bytes, void *stream);
+
+/* Backward of C = A . B for L = sum(C * G):
+ *   dA[m, k] = G . B^T   (contraction over n; B's tiles read along rows)
+ *   dB[k, n] = A^T . G   (contraction over m; the transposed product)
+ * A: m x k (lda >= k), B: k x n (ldb >= n), G: m x n (ldg >= n),
+ * dA: m x k (ldda >= k), dB: k x n (lddb >= n).  Either output may be NULL
+ * to skip it.  Both products follow the same schedule `s`, run one after
+ * the other on `stream` and may share the workspace.  Storage types as for
+ * hs_gemm (G has the input type). */
+hs_status hs_gemm_backward(int64_t m, int64_t n, int64_t k, hs_dtype dtype, hs_schedule s,
+                           const void *A, int64_t lda, const void *B, int64_t ldb,
+                           const void *G, int64_t ldg,
+                           void *dA, int64_t ldda, void *dB, int64_t lddb,
+                           void *ws, size_t ws_bytes, void *stream);
+
+/* Kernel timing for measurement.  Between hs_profile_begin() and
+ * hs_profile_end(), every launch of the main (MFMA) kernel of any call made
+ * from this process is bracketed by a pair of HIP events on its stream.
+ * hs_profile_end() waits for those events and returns the summed elapsed
+ * milliseconds and the number of launches.  Not thread-safe; host only.
+ * Returns HS_ERR_INVALID_VALUE if profiling was not begun. */
+hs_status hs_profile_begin(void);
+hs_status hs_profile_end(double *total_ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HS_H */

@@ -17,6 +17,12 @@
  * All matrices are dense, row-major, with explicit leading dimensions
  * (elements between consecutive rows).  Inputs are the stored values of the
  * caller's matrices promoted to double.
+ *
+ * Loop order: where the contraction runs over rows of a row-major operand,
+ * an output row is accumulated as acc[j] += a_ip * b_pj for p = 0, 1, ...
+ * (the p-loop outside the j-loop).  Each acc[j] still receives its terms one
+ * at a time in ascending p, so every element is bitwise the same sum as the
+ * textbook i-j-p loop; only the memory walk differs.
  */
 #include <stdint.h>
 #include <stddef.h>
@@ -31,11 +37,12 @@ void hs_oracle_gemm(int64_t m, int64_t n, int64_t k,
     int64_t i;
 #pragma omp parallel for schedule(static)
     for (i = 0; i < m; ++i) {
-        for (int64_t j = 0; j < n; ++j) {
-            double s = 0.0;
-            for (int64_t p = 0; p < k; ++p)
-                s += A[i * lda + p] * B[p * ldb + j];
-            C[i * ldc + j] = s;
+        double *c = C + i * ldc;
+        for (int64_t j = 0; j < n; ++j) c[j] = 0.0;
+        for (int64_t p = 0; p < k; ++p) {
+            const double a = A[i * lda + p];
+            const double *b = B + p * ldb;
+            for (int64_t j = 0; j < n; ++j) c[j] += a * b[j];
         }
     }
 }
@@ -50,11 +57,12 @@ void hs_oracle_gemm_tn(int64_t m, int64_t n, int64_t k,
     int64_t i;
 #pragma omp parallel for schedule(static)
     for (i = 0; i < m; ++i) {
-        for (int64_t j = 0; j < n; ++j) {
-            double s = 0.0;
-            for (int64_t p = 0; p < k; ++p)
-                s += A[p * lda + i] * B[p * ldb + j];
-            C[i * ldc + j] = s;
+        double *c = C + i * ldc;
+        for (int64_t j = 0; j < n; ++j) c[j] = 0.0;
+        for (int64_t p = 0; p < k; ++p) {
+            const double a = A[p * lda + i];
+            const double *b = B + p * ldb;
+            for (int64_t j = 0; j < n; ++j) c[j] += a * b[j];
         }
     }
 }
@@ -100,11 +108,12 @@ void hs_oracle_backward(int64_t m, int64_t n, int64_t k,
     if (dB) {
 #pragma omp parallel for schedule(static)
         for (i = 0; i < k; ++i) {
-            for (int64_t j = 0; j < n; ++j) {
-                double s = 0.0;
-                for (int64_t q = 0; q < m; ++q)
-                    s += A[q * lda + i] * G[q * ldg + j];
-                dB[i * lddb + j] = s;
+            double *c = dB + i * lddb;
+            for (int64_t j = 0; j < n; ++j) c[j] = 0.0;
+            for (int64_t q = 0; q < m; ++q) {
+                const double a = A[q * lda + i];
+                const double *g = G + q * ldg;
+                for (int64_t j = 0; j < n; ++j) c[j] += a * g[j];
             }
         }
     }
@@ -122,11 +131,12 @@ void hs_oracle_gemm_rows(int64_t n, int64_t k,
 #pragma omp parallel for schedule(static)
     for (t = 0; t < nrows; ++t) {
         const int64_t i = rows[t];
-        for (int64_t j = 0; j < n; ++j) {
-            double s = 0.0;
-            for (int64_t p = 0; p < k; ++p)
-                s += A[i * lda + p] * B[p * ldb + j];
-            out[t * ldo + j] = s;
+        double *c = out + t * ldo;
+        for (int64_t j = 0; j < n; ++j) c[j] = 0.0;
+        for (int64_t p = 0; p < k; ++p) {
+            const double a = A[i * lda + p];
+            const double *b = B + p * ldb;
+            for (int64_t j = 0; j < n; ++j) c[j] += a * b[j];
         }
     }
 }
@@ -142,11 +152,12 @@ void hs_oracle_gemm_tn_rows(int64_t n, int64_t k,
 #pragma omp parallel for schedule(static)
     for (t = 0; t < nrows; ++t) {
         const int64_t i = rows[t];
-        for (int64_t j = 0; j < n; ++j) {
-            double s = 0.0;
-            for (int64_t p = 0; p < k; ++p)
-                s += A[p * lda + i] * B[p * ldb + j];
-            out[t * ldo + j] = s;
+        double *c = out + t * ldo;
+        for (int64_t j = 0; j < n; ++j) c[j] = 0.0;
+        for (int64_t p = 0; p < k; ++p) {
+            const double a = A[p * lda + i];
+            const double *b = B + p * ldb;
+            for (int64_t j = 0; j < n; ++j) c[j] += a * b[j];
         }
     }
 }

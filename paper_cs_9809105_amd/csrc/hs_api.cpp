@@ -1,0 +1,381 @@
+// hs_api.cpp -- host side of the C ABI declared in include/hs.h: argument
+// validation, the schedule (bases of Sec. 5.2.1), workspace planning and the
+// launch sequence pack -> main loop -> back-shift on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <limits>
+#include <utility>
+#include <vector>
+
+#include "hs.h"
+#include "hs_internal.h"
+
+namespace hs {
+hipError_t launch_pack(int kind, int kmajor, const PackArgs &a, hipStream_t st);
+hipError_t launch_mm(int fam, int form, const MainArgs &a, hipStream_t st);
+hipError_t launch_backshift(int f64, const void *W, int64_t plane, int K, int64_t M, int64_t N,
+                            void *Cout, int64_t ldc, hipStream_t st);
+hipError_t launch_fill_zero(int f64, void *Cout, int64_t M, int64_t N, int64_t ldc, hipStream_t st);
+hipError_t launch_gemv(int f64, const GemvArgs &a, hipStream_t st);
+int mm_tile_rows(int fam);
+int mm_tile_cols(int fam);
+int mm_chunks_per_stage(int fam, int form);
+}  // namespace hs
+
+using namespace hs;
+
+namespace {
+
+const int kMaxP = 4096;
+const size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+struct FormInfo {
+    int fam, form, pack, in_esz, out_f64, packed_esz;
+};
+
+bool form_info(hs_dtype dt, FormInfo *f) {
+    switch (dt) {
+        case HS_F64: *f = {FAM_F64, 0, PK_F64, 8, 1, 8}; return true;
+        case HS_F32: *f = {FAM_F32, 0, PK_F32, 4, 0, 4}; return true;
+        case HS_BF16: *f = {FAM_BF16, 0, PK_B16, 2, 0, 2}; return true;
+        case HS_F16: *f = {FAM_F16, 0, PK_B16, 2, 0, 2}; return true;
+        case HS_SPLIT3_BF16: *f = {FAM_BF16, 1, PK_SPLIT3, 4, 0, 2}; return true;
+        default: return false;
+    }
+}
+
+// Default K: the divisor of p minimising the shift count K + p/K - 1
+// (Thm. on minimal length, Sec. 4.4); ties go to the smaller K.
+int default_K(int p) {
+    int best = 1, cost = std::numeric_limits<int>::max();
+    for (int K = 1; K <= p; ++K)
+        if (p % K == 0 && K + p / K - 1 < cost) { cost = K + p / K - 1; best = K; }
+    return best;
+}
+
+struct Plan {
+    FormInfo f;
+    int p, K, Kt;
+    int64_t M, N, Kd;
+    OperandGeom ga, gb;
+    size_t off_a, off_b, off_w, total;
+};
+
+// Geometry of one product C[M,N] = X[M,Kd] Y[Kd,N] under schedule (p, K).
+hs_status make_plan(int64_t M, int64_t N, int64_t Kd, hs_dtype dt, hs_schedule s, Plan *P) {
+    if (!form_info(dt, &P->f)) return HS_ERR_NOT_SUPPORTED;
+    hs_schedule r;
+    hs_status st = hs_schedule_resolve(s, &r);
+    if (st != HS_OK) return st;
+    if (M < 0 || N < 0 || Kd < 0) return HS_ERR_INVALID_VALUE;
+    P->p = r.p; P->K = r.K; P->Kt = r.p / r.K;
+    P->M = M; P->N = N; P->Kd = Kd;
+    const int BMT = mm_tile_rows(P->f.fam), BNT = mm_tile_cols(P->f.fam);
+    const int CPS = mm_chunks_per_stage(P->f.fam, P->f.form);
+    if (P->K > BMT) return HS_ERR_NOT_SUPPORTED;   // K groups of >= 1 row per tile
+    const int p = P->p;
+    const int KC = 32 / P->f.packed_esz;
+    const int64_t S_r = std::max<int64_t>(1, ceil_div(M, p));
+    const int64_t S_k = std::max<int64_t>(1, ceil_div(Kd, p));
+    const int64_t nch = ceil_div(ceil_div(S_k, KC), CPS) * CPS;
+    const int MS = (int)std::min<int64_t>(BMT / P->K, S_r);
+    const int NP = P->f.form == 1 ? 3 : 1;
+
+    OperandGeom &a = P->ga;
+    a.R = M; a.Kd = Kd; a.striped = 1; a.S_r = S_r; a.grp_rows = MS;
+    a.GS = ceil_div(S_r, MS); a.n_groups = (int64_t)p * a.GS; a.p = p;
+    a.S_k = S_k; a.nch = nch; a.chunk_bytes = 32; a.pieces = NP;
+    a.piece_bytes = a.n_groups * p * nch * MS * 32;
+
+    OperandGeom &b = P->gb;
+    b.R = N; b.Kd = Kd; b.striped = 0; b.S_r = 0; b.grp_rows = BNT;
+    b.GS = ceil_div(N, BNT); b.n_groups = b.GS; b.p = p;
+    b.S_k = S_k; b.nch = nch; b.chunk_bytes = 32; b.pieces = NP;
+    b.piece_bytes = b.n_groups * p * nch * BNT * 32;
+
+    const int64_t nwg = (int64_t)p * a.GS * b.GS;
+    if (nwg > std::numeric_limits<int32_t>::max()) return HS_ERR_NOT_SUPPORTED;
+
+    size_t off = 0;
+    P->off_a = off; off = align_up(off + (size_t)(a.piece_bytes * NP));
+    P->off_b = off; off = align_up(off + (size_t)(b.piece_bytes * NP));
+    P->off_w = off;
+    if (P->K > 1) off = align_up(off + (size_t)P->K * M * N * (P->f.out_f64 ? 8 : 4));
+    P->total = (M == 0 || N == 0 || Kd == 0) ? 0 : off;
+    return HS_OK;
+}
+
+bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+// ---------------------------------------------------------------------------
+// kernel timing (hs_profile_begin / hs_profile_end)
+// ---------------------------------------------------------------------------
+bool g_prof = false;
+std::vector<std::pair<hipEvent_t, hipEvent_t>> g_events;
+
+struct Operand {
+    const void *ptr;
+    int64_t ld;
+    int kmajor;   // 1: contraction index contiguous
+};
+
+hs_status launch_status(hipError_t e) { return e == hipSuccess ? HS_OK : HS_ERR_LAUNCH_FAILED; }
+
+// One product through the hyper-systolic path.  The plan must come from
+// make_plan with the same sizes; ws holds at least plan.total bytes.
+hs_status run_product(const Plan &P, const Operand &X, const Operand &Y, void *out, int64_t ldo,
+                      void *ws, hipStream_t stream) {
+    const int f64 = P.f.out_f64;
+    if (P.M == 0 || P.N == 0) return HS_OK;
+    if (P.Kd == 0) return launch_status(launch_fill_zero(f64, out, P.M, P.N, ldo, stream));
+    uint8_t *w = (uint8_t *)ws;
+
+    PackArgs pa{};
+    pa.src = X.ptr; pa.ld = X.ld; pa.g = P.ga; pa.dst = w + P.off_a;
+    pa.total_units = P.ga.n_groups * P.ga.p * P.ga.nch * P.ga.grp_rows * (P.ga.chunk_bytes / 16);
+    hipError_t e = launch_pack(P.f.pack, X.kmajor, pa, stream);
+    if (e != hipSuccess) return HS_ERR_LAUNCH_FAILED;
+    PackArgs pb{};
+    pb.src = Y.ptr; pb.ld = Y.ld; pb.g = P.gb; pb.dst = w + P.off_b;
+    pb.total_units = P.gb.n_groups * P.gb.p * P.gb.nch * P.gb.grp_rows * (P.gb.chunk_bytes / 16);
+    e = launch_pack(P.f.pack, Y.kmajor, pb, stream);
+    if (e != hipSuccess) return HS_ERR_LAUNCH_FAILED;
+
+    MainArgs m{};
+    m.A = w + P.off_a; m.a_piece = P.ga.piece_bytes;
+    m.B = w + P.off_b; m.b_piece = P.gb.piece_bytes;
+    const bool partials = P.K > 1;
+    m.out = partials ? (void *)(w + P.off_w) : out;
+    m.ldo = partials ? P.N : ldo;
+    m.plane = P.M * P.N;
+    m.p = P.p; m.K = P.K; m.Kt = P.Kt;
+    m.MS = P.ga.grp_rows; m.GS = P.ga.GS; m.nch = P.ga.nch; m.S_r = P.ga.S_r;
+    m.M = P.M; m.N = P.N; m.n_ntiles = P.gb.GS; m.out_f64 = f64;
+
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (g_prof) {
+        if (hipEventCreate(&ev0) != hipSuccess || hipEventCreate(&ev1) != hipSuccess)
+            return HS_ERR_LAUNCH_FAILED;
+        hipEventRecord(ev0, stream);
+    }
+    e = launch_mm(P.f.fam, P.f.form, m, stream);
+    if (g_prof) {
+        hipEventRecord(ev1, stream);
+        g_events.push_back({ev0, ev1});
+    }
+    if (e != hipSuccess) return HS_ERR_LAUNCH_FAILED;
+    if (partials)
+        return launch_status(launch_backshift(f64, w + P.off_w, P.M * P.N, P.K, P.M, P.N, out, ldo, stream));
+    return HS_OK;
+}
+
+hs_status check_mat(const void *p, int64_t rows, int64_t cols, int64_t ld, size_t esz) {
+    if (rows < 0 || cols < 0) return HS_ERR_INVALID_VALUE;
+    if (ld < std::max<int64_t>(1, cols)) return HS_ERR_INVALID_VALUE;
+    if (rows > 0 && cols > 0) {
+        if (!p) return HS_ERR_INVALID_VALUE;
+        if (!aligned(p, esz)) return HS_ERR_INVALID_VALUE;
+    }
+    return HS_OK;
+}
+
+hs_status check_ws(const Plan &P, const void *ws, size_t ws_bytes) {
+    if (P.total == 0) return HS_OK;
+    if (!ws) return HS_ERR_WORKSPACE_TOO_SMALL;
+    if (!aligned(ws, kAlign)) return HS_ERR_INVALID_VALUE;
+    if (ws_bytes < P.total) return HS_ERR_WORKSPACE_TOO_SMALL;
+    return HS_OK;
+}
+
+#define HS_TRY(x)                          \
+    do {                                   \
+        hs_status _s = (x);                \
+        if (_s != HS_OK) return _s;        \
+    } while (0)
+
+}  // namespace
+
+extern "C" {
+
+const char *hs_status_string(hs_status s) {
+    switch (s) {
+        case HS_OK: return "HS_OK";
+        case HS_ERR_INVALID_VALUE: return "HS_ERR_INVALID_VALUE: invalid argument";
+        case HS_ERR_NOT_SUPPORTED: return "HS_ERR_NOT_SUPPORTED: dtype or size not supported for this call";
+        case HS_ERR_WORKSPACE_TOO_SMALL: return "HS_ERR_WORKSPACE_TOO_SMALL: workspace smaller than hs_workspace_size()";
+        case HS_ERR_LAUNCH_FAILED: return "HS_ERR_LAUNCH_FAILED: the HIP runtime rejected a launch";
+    }
+    return "unknown hs_status";
+}
+
+hs_status hs_schedule_resolve(hs_schedule in, hs_schedule *out) {
+    if (!out) return HS_ERR_INVALID_VALUE;
+    if (in.p < 1 || in.p > kMaxP || in.K < 0) return HS_ERR_INVALID_VALUE;
+    int K = in.K == 0 ? default_K(in.p) : in.K;
+    if (K > in.p || in.p % K != 0) return HS_ERR_INVALID_VALUE;
+    out->p = in.p;
+    out->K = K;
+    return HS_OK;
+}
+
+hs_status hs_schedule_table(hs_schedule s, int32_t *out, size_t cap) {
+    hs_schedule r;
+    HS_TRY(hs_schedule_resolve(s, &r));
+    const int p = r.p, K = r.K, Kt = p / K;
+    if (!out || cap < (size_t)2 * p * p) return HS_ERR_INVALID_VALUE;
+    size_t t = 0;
+    for (int v = 0; v < p; ++v)
+        for (int j = 0; j < Kt; ++j)
+            for (int l = 0; l < K; ++l) {
+                out[t++] = ((v - l) % p + p) % p;   // output stripe: partial c^l of v
+                out[t++] = (v + j * K) % p;         // travelling block after j shifts by K
+            }
+    return HS_OK;
+}
+
+size_t hs_workspace_size(hs_op op, int64_t m, int64_t n, int64_t k, hs_dtype dtype, hs_schedule s) {
+    const size_t bad = std::numeric_limits<size_t>::max();
+    Plan P;
+    switch (op) {
+        case HS_OP_GEMM:
+        case HS_OP_GEMM_TN:
+            if (make_plan(m, n, k, dtype, s, &P) != HS_OK) return bad;
+            return P.total;
+        case HS_OP_GEMV: {
+            if (dtype != HS_F32 && dtype != HS_F64) return bad;
+            hs_schedule r;
+            if (hs_schedule_resolve(s, &r) != HS_OK || m < 0 || n < 0) return bad;
+            return 0;
+        }
+        case HS_OP_BACKWARD: {
+            Plan Pa, Pb;
+            if (make_plan(m, k, n, dtype, s, &Pa) != HS_OK) return bad;
+            if (make_plan(k, n, m, dtype, s, &Pb) != HS_OK) return bad;
+            return std::max(Pa.total, Pb.total);
+        }
+    }
+    return bad;
+}
+
+hs_status hs_gemm(int64_t m, int64_t n, int64_t k, hs_dtype dtype, hs_schedule s,
+                  const void *A, int64_t lda, const void *B, int64_t ldb,
+                  void *C, int64_t ldc, void *ws, size_t ws_bytes, void *stream) {
+    Plan P;
+    HS_TRY(make_plan(m, n, k, dtype, s, &P));
+    HS_TRY(check_mat(A, m, k, lda, P.f.in_esz));
+    HS_TRY(check_mat(B, k, n, ldb, P.f.in_esz));
+    HS_TRY(check_mat(C, m, n, ldc, P.f.out_f64 ? 8 : 4));
+    HS_TRY(check_ws(P, ws, ws_bytes));
+    return run_product(P, Operand{A, lda, 1}, Operand{B, ldb, 0}, C, ldc, ws, (hipStream_t)stream);
+}
+
+hs_status hs_gemm_tn(int64_t m, int64_t n, int64_t k, hs_dtype dtype, hs_schedule s,
+                     const void *A, int64_t lda, const void *B, int64_t ldb,
+                     void *C, int64_t ldc, void *ws, size_t ws_bytes, void *stream) {
+    Plan P;
+    HS_TRY(make_plan(m, n, k, dtype, s, &P));
+    HS_TRY(check_mat(A, k, m, lda, P.f.in_esz));
+    HS_TRY(check_mat(B, k, n, ldb, P.f.in_esz));
+    HS_TRY(check_mat(C, m, n, ldc, P.f.out_f64 ? 8 : 4));
+    HS_TRY(check_ws(P, ws, ws_bytes));
+    return run_product(P, Operand{A, lda, 0}, Operand{B, ldb, 0}, C, ldc, ws, (hipStream_t)stream);
+}
+
+hs_status hs_gemv(int64_t m, int64_t n, hs_dtype dtype, hs_schedule s,
+                  const void *A, int64_t lda, const void *x, void *y,
+                  void *ws, size_t ws_bytes, void *stream) {
+    (void)ws;
+    (void)ws_bytes;
+    if (dtype != HS_F32 && dtype != HS_F64) return HS_ERR_NOT_SUPPORTED;
+    hs_schedule r;
+    HS_TRY(hs_schedule_resolve(s, &r));
+    const size_t esz = dtype == HS_F64 ? 8 : 4;
+    HS_TRY(check_mat(A, m, n, lda, esz));
+    if (n > 0 && m > 0 && (!x || !aligned(x, esz))) return HS_ERR_INVALID_VALUE;
+    if (m > 0 && (!y || !aligned(y, esz))) return HS_ERR_INVALID_VALUE;
+    if (m == 0) return HS_OK;
+    hipStream_t st = (hipStream_t)stream;
+    const int f64 = dtype == HS_F64;
+    if (n == 0) return launch_status(launch_fill_zero(f64, y, m, 1, 1, st));
+    GemvArgs g{};
+    g.A = A; g.lda = lda; g.x = x; g.y = y; g.m = m; g.n = n;
+    g.p = r.p; g.K = r.K; g.Kt = r.p / r.K;
+    g.S_r = std::max<int64_t>(1, ceil_div(m, r.p));
+    g.S_k = std::max<int64_t>(1, ceil_div(n, r.p));
+    const int VE = f64 ? 2 : 4;
+    g.vec = (g.S_k % VE == 0 && lda % VE == 0 && n % VE == 0 && aligned(A, 16) && aligned(x, 16)) ? 1 : 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (g_prof) {
+        if (hipEventCreate(&ev0) != hipSuccess || hipEventCreate(&ev1) != hipSuccess)
+            return HS_ERR_LAUNCH_FAILED;
+        hipEventRecord(ev0, st);
+    }
+    hipError_t e = launch_gemv(f64, g, st);
+    if (g_prof) {
+        hipEventRecord(ev1, st);
+        g_events.push_back({ev0, ev1});
+    }
+    return launch_status(e);
+}
+
+hs_status hs_gemm_backward(int64_t m, int64_t n, int64_t k, hs_dtype dtype, hs_schedule s,
+                           const void *A, int64_t lda, const void *B, int64_t ldb,
+                           const void *G, int64_t ldg,
+                           void *dA, int64_t ldda, void *dB, int64_t lddb,
+                           void *ws, size_t ws_bytes, void *stream) {
+    Plan Pa, Pb;
+    HS_TRY(make_plan(m, k, n, dtype, s, &Pa));   // dA[m,k] = G[m,n] . B[k,n]^T
+    HS_TRY(make_plan(k, n, m, dtype, s, &Pb));   // dB[k,n] = A[m,k]^T . G[m,n]
+    const size_t oesz = Pa.f.out_f64 ? 8 : 4;
+    HS_TRY(check_mat(G, m, n, ldg, Pa.f.in_esz));
+    if (dA) {
+        HS_TRY(check_mat(B, k, n, ldb, Pa.f.in_esz));
+        HS_TRY(check_mat(dA, m, k, ldda, oesz));
+        HS_TRY(check_ws(Pa, ws, ws_bytes));
+    }
+    if (dB) {
+        HS_TRY(check_mat(A, m, k, lda, Pb.f.in_esz));
+        HS_TRY(check_mat(dB, k, n, lddb, oesz));
+        HS_TRY(check_ws(Pb, ws, ws_bytes));
+    }
+    hipStream_t st = (hipStream_t)stream;
+    if (dA) HS_TRY(run_product(Pa, Operand{G, ldg, 1}, Operand{B, ldb, 1}, dA, ldda, ws, st));
+    if (dB) HS_TRY(run_product(Pb, Operand{A, lda, 0}, Operand{G, ldg, 0}, dB, lddb, ws, st));
+    return HS_OK;
+}
+
+hs_status hs_profile_begin(void) {
+    g_prof = true;
+    return HS_OK;
+}
+
+hs_status hs_profile_end(double *total_ms, int64_t *launches) {
+    if (!g_prof) return HS_ERR_INVALID_VALUE;
+    g_prof = false;
+    double tot = 0.0;
+    int64_t n = 0;
+    hs_status st = HS_OK;
+    for (auto &pr : g_events) {
+        float ms = 0.f;
+        if (hipEventSynchronize(pr.second) != hipSuccess ||
+            hipEventElapsedTime(&ms, pr.first, pr.second) != hipSuccess)
+            st = HS_ERR_LAUNCH_FAILED;
+        tot += ms;
+        ++n;
+        hipEventDestroy(pr.first);
+        hipEventDestroy(pr.second);
+    }
+    g_events.clear();
+    if (total_ms) *total_ms = tot;
+    if (launches) *launches = n;
+    return st;
+}
+
+}  // extern "C"

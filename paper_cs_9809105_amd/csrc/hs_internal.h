@@ -1,0 +1,95 @@
+// hs_internal.h -- structures shared by the host API and the HIP kernels.
+//
+// Packed operand layout ("pack").  A product C[M,N] = sum_k X[M,k] Y[k,N]
+// sees two operands, each as a matrix of R "rows" (the non-contraction
+// dimension) by Kd contraction elements:
+//   * the static operand X (R = M) is cut into p row stripes of S_r rows
+//     (virtual processor v owns stripe v, Sec. 5.2.2); each stripe into GS
+//     groups of MS rows, zero padded;
+//   * the travelling operand Y (R = N, one row per output column) is cut into
+//     groups of BN rows (the workgroup column tile);
+//   * the contraction is cut into p blocks of S_k elements (block kb is the
+//     stripe of Y that a virtual processor holds after kb-v shifts), each
+//     padded with zeros to nch chunks of KC elements (32 or 64 bytes).
+// Packed bytes: [piece][group][kb][chunk][row in group][chunk bytes].
+// One (group, kb, chunk) is therefore a contiguous run of rows x 32 bytes,
+// which is exactly one HBM->LDS fetch of a pipeline stage.
+#pragma once
+#include <stdint.h>
+#include <stddef.h>
+
+namespace hs {
+
+enum Family : int { FAM_F64 = 0, FAM_F32 = 1, FAM_BF16 = 2, FAM_F16 = 3, FAM_FP8 = 4 };
+
+// What the pack kernel converts from/to.
+enum PackKind : int {
+    PK_F64 = 0,      // f64 -> f64
+    PK_F32 = 1,      // f32 -> f32
+    PK_B16 = 2,      // 16-bit -> same 16-bit (bf16 or f16 copy)
+    PK_SPLIT3 = 3,   // f32 -> three bf16 pieces
+    PK_FP8 = 4,      // f32 -> e4m3 q0 (+ q1) with per-tile scales
+};
+
+struct OperandGeom {
+    int64_t R;        // logical rows
+    int64_t Kd;       // contraction length
+    int striped;      // 1: p stripes of S_r rows, groups of MS; 0: groups of grp_rows
+    int64_t S_r;      // stripe height (striped) -- ceil(R / p)
+    int grp_rows;     // rows per group (MS or BN)
+    int64_t GS;       // groups per stripe (striped) or total groups (tiles)
+    int64_t n_groups; // total groups
+    int p;
+    int64_t S_k;      // contraction block length -- ceil(Kd / p)
+    int64_t nch;      // chunks per block (padded)
+    int chunk_bytes;  // 32 (f64, f32, 16-bit) or 64 (fp8)
+    int pieces;       // planes written
+    int64_t piece_bytes;
+};
+
+struct PackArgs {
+    const void *src;
+    int64_t ld;
+    OperandGeom g;
+    void *dst;
+    uint8_t *scale_dst;   // fp8 only: [piece][group][kb][chunk][row][2]
+    int64_t scale_piece_bytes;
+    const float *tile_scale; // fp8 only: per 128x128 tile exponent info
+    int64_t tiles_r, tiles_k;
+    int64_t total_units;
+};
+
+struct MainArgs {
+    const uint8_t *A;        // packed static operand, piece 0
+    int64_t a_piece;         // bytes between pieces
+    const uint8_t *B;        // packed travelling operand
+    int64_t b_piece;
+    const uint8_t *a_scale;  // fp8 only
+    int64_t a_scale_piece;
+    const uint8_t *b_scale;
+    int64_t b_scale_piece;
+    void *out;               // partial planes (K > 1) or the result (K == 1)
+    int64_t ldo;             // row stride of out (elements)
+    int64_t plane;           // elements between partial planes
+    int p, K, Kt;
+    int MS;                  // static-operand rows per group
+    int64_t GS;              // groups per stripe
+    int64_t nch;             // chunks per contraction block
+    int64_t S_r;             // stripe height
+    int64_t M, N;
+    int64_t n_ntiles;
+    int out_f64;             // out element type: 1 double, 0 float
+};
+
+struct GemvArgs {
+    const void *A;
+    int64_t lda;
+    const void *x;
+    void *y;
+    int64_t m, n;
+    int p, K, Kt;
+    int64_t S_r, S_k;
+    int vec;                 // 1: 16-byte loads are legal
+};
+
+}  // namespace hs

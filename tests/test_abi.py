@@ -1,0 +1,215 @@
+"""Host-side tests of the C ABI (CPU only: no kernel is launched).
+
+* the library loads and exports every function include/hs.h declares;
+* the schedule (index map) equals the event trace of the literal
+  Algorithm HYPER-SYSTOLIC simulator applied to C^T = B^T A^T;
+* every invalid argument is rejected with its status code before any launch.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import bases, ring
+from paper_cs_9809105_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hs.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(hs_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(B.LIB_PATH)
+    names = _declared()
+    assert {"hs_gemm", "hs_gemm_tn", "hs_gemv", "hs_gemm_backward"} <= set(names)
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_binding_names_match_abi():
+    import paper_cs_9809105_amd as pkg
+    for name in _declared():
+        assert hasattr(B, name), name
+    for name in ("hs_gemm", "hs_gemm_tn", "hs_gemv", "hs_gemm_backward"):
+        assert getattr(pkg, name) is getattr(B, name)
+
+
+def test_status_strings():
+    for s in range(5):
+        assert B.hs_status_string(s).startswith("HS_")
+    assert B.hs_status_string(99) == "unknown hs_status"
+
+
+@pytest.mark.parametrize("p", [1, 2, 4, 6, 9, 12, 16, 36, 64, 100])
+def test_default_K_minimises_shifts(p):
+    _, K = B.hs_schedule_resolve(p, 0)
+    cost = K + p // K - 1
+    assert p % K == 0
+    assert cost == min(d + p // d - 1 for d in range(1, p + 1) if p % d == 0)
+    if int(round(p ** 0.5)) ** 2 == p:
+        assert K == int(round(p ** 0.5))
+
+
+@pytest.mark.parametrize("p,K", [(0, 0), (-1, 1), (4097, 1), (8, 3), (8, 16), (6, -2)])
+def test_invalid_schedules(p, K):
+    with pytest.raises(B.HsError) as e:
+        B.hs_schedule_resolve(p, K)
+    assert e.value.status == B.HS_ERR_INVALID_VALUE
+
+
+def _sim_table(p, K):
+    """(output stripe, contraction block) per (v, j, l) from the literal simulator.
+
+    The paper's algorithm keeps columns and moves A; the library keeps rows
+    and moves B, i.e. it runs the algorithm on C^T = B^T A^T.  Paper element
+    PA[r, c] stands for B block (c, r) and PB[r, c] for A block (c, r)."""
+    PA, PB = ring.leaves("PA", p), ring.leaves("PB", p)
+    trace = []
+    ring.hyper_systolic(PA, PB, K, ring.Term(), trace=trace)
+    ev = {}
+    for (i, j, l, n, ae, be) in trace:
+        assert ae.c == be.r                     # contraction blocks agree
+        ev.setdefault((i - 1, j - 1, l - 1), set()).add((be.c, ae.c))
+    rows = []
+    for v in range(p):
+        for j in range(p // K):
+            for l in range(K):
+                s = ev[(v, j, l)]
+                assert len(s) == 1
+                rows.append(next(iter(s)))
+    return np.array(rows, dtype=np.int32)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 6, 8, 9, 12, 16])
+def test_schedule_table_equals_literal_algorithm(p):
+    for K in [d for d in range(1, p + 1) if p % d == 0]:
+        assert np.array_equal(B.hs_schedule_table(p, K), _sim_table(p, K)), (p, K)
+
+
+@pytest.mark.parametrize("p,K", [(64, 8), (64, 2), (256, 16), (48, 6), (4096, 64)])
+def test_schedule_covers_every_block_product_once(p, K):
+    t = B.hs_schedule_table(p, K)
+    pairs = {(int(r), int(kb)) for r, kb in t}
+    assert len(t) == p * p and len(pairs) == p * p
+    # base A: successive steps of one virtual processor differ by K
+    t3 = t.reshape(p, p // K, K, 2)
+    assert np.all((np.diff(t3[:, :, 0, 1], axis=1) % p) == K % p)
+    # pre-shift base B and back-shift base C: partial l of v feeds stripe v - l
+    v = np.arange(p)[:, None]
+    assert np.array_equal(t3[:, 0, :, 0], (v - np.arange(K)[None, :]) % p)
+    # shift count of Thm. GAIN3 for this (p, K)
+    assert bases.shifts_matrix_product(K, p // K) == K + p // K - 1
+
+
+def test_schedule_table_small_buffer():
+    buf = (ctypes.c_int32 * 7)()
+    st = B.lib().hs_schedule_table(B.hs_schedule(4, 2), buf, 7)
+    assert st == B.HS_ERR_INVALID_VALUE
+
+
+def test_workspace_sizes():
+    ws = B.hs_workspace_size
+    assert ws(B.HS_OP_GEMM, 0, 10, 10, "f32", 2) == 0
+    assert ws(B.HS_OP_GEMM, 10, 10, 0, "f32", 2) == 0
+    assert ws(B.HS_OP_GEMV, 100, 100, 0, "f32", 4) == 0
+    assert ws(B.HS_OP_GEMV, 100, 100, 0, "bf16", 4) == B.SIZE_MAX
+    assert ws(B.HS_OP_GEMM, 10, 10, 10, "f32", 3, 2) == B.SIZE_MAX
+    assert ws(B.HS_OP_GEMM, 10, 10, 10, 99, 2) == B.SIZE_MAX
+    s1 = ws(B.HS_OP_GEMM, 1024, 1024, 1024, "f32", 8, 1)
+    s2 = ws(B.HS_OP_GEMM, 1024, 1024, 1024, "f32", 8, 2)
+    assert s2 - s1 >= 2 * 1024 * 1024 * 4          # K partial planes
+    s3 = ws(B.HS_OP_GEMM, 1024, 1024, 1024, "split3_bf16", 8, 1)
+    assert s3 > s1                                 # three bf16 pieces per operand
+    for n in (B.HS_OP_GEMM, B.HS_OP_GEMM_TN, B.HS_OP_BACKWARD):
+        assert ws(n, 512, 384, 256, "f64", 16, 4) % 256 == 0
+    assert ws(B.HS_OP_BACKWARD, 64, 128, 32, "f32", 4, 2) >= ws(B.HS_OP_GEMM, 64, 32, 128, "f32", 4, 2)
+
+
+# ---------------------------------------------------------------------------
+# argument validation: every failure returns before any launch
+# ---------------------------------------------------------------------------
+FAKE = 1 << 20          # aligned, never dereferenced on the host
+
+
+def _gemm(**kw):
+    a = dict(m=8, n=8, k=8, dt=B.HS_F32, p=2, K=0, A=FAKE, lda=8, Bp=FAKE, ldb=8, C=FAKE,
+             ldc=8, ws=FAKE, wsb=1 << 30, st=None)
+    a.update(kw)
+    return B.lib().hs_gemm(a["m"], a["n"], a["k"], a["dt"], B.hs_schedule(a["p"], a["K"]), a["A"],
+                           a["lda"], a["Bp"], a["ldb"], a["C"], a["ldc"], a["ws"], a["wsb"], a["st"])
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(m=-1), B.HS_ERR_INVALID_VALUE),
+    (dict(lda=7), B.HS_ERR_INVALID_VALUE),
+    (dict(ldb=4), B.HS_ERR_INVALID_VALUE),
+    (dict(ldc=0), B.HS_ERR_INVALID_VALUE),
+    (dict(A=None), B.HS_ERR_INVALID_VALUE),
+    (dict(Bp=None), B.HS_ERR_INVALID_VALUE),
+    (dict(C=None), B.HS_ERR_INVALID_VALUE),
+    (dict(A=FAKE + 2), B.HS_ERR_INVALID_VALUE),
+    (dict(p=0), B.HS_ERR_INVALID_VALUE),
+    (dict(p=4, K=3), B.HS_ERR_INVALID_VALUE),
+    (dict(dt=17), B.HS_ERR_NOT_SUPPORTED),
+    (dict(ws=None), B.HS_ERR_WORKSPACE_TOO_SMALL),
+    (dict(wsb=16), B.HS_ERR_WORKSPACE_TOO_SMALL),
+    (dict(ws=FAKE + 64), B.HS_ERR_INVALID_VALUE),
+    (dict(p=512, K=512), B.HS_ERR_NOT_SUPPORTED),
+])
+def test_gemm_rejects(kw, code):
+    assert _gemm(**kw) == code
+
+
+def test_gemm_tn_rejects_bad_lda():
+    L = B.lib()
+    # A is k x m: lda must be >= m
+    st = L.hs_gemm_tn(8, 8, 16, B.HS_F32, B.hs_schedule(2, 0), FAKE, 4, FAKE, 8, FAKE, 8,
+                      FAKE, 1 << 30, None)
+    assert st == B.HS_ERR_INVALID_VALUE
+
+
+def test_gemv_rejects():
+    L = B.lib()
+    s = B.hs_schedule(2, 0)
+    assert L.hs_gemv(8, 8, B.HS_BF16, s, FAKE, 8, FAKE, FAKE, None, 0, None) == B.HS_ERR_NOT_SUPPORTED
+    assert L.hs_gemv(8, 8, B.HS_F32, s, FAKE, 4, FAKE, FAKE, None, 0, None) == B.HS_ERR_INVALID_VALUE
+    assert L.hs_gemv(8, 8, B.HS_F32, s, FAKE, 8, None, FAKE, None, 0, None) == B.HS_ERR_INVALID_VALUE
+    assert L.hs_gemv(8, 8, B.HS_F32, s, FAKE, 8, FAKE, None, None, 0, None) == B.HS_ERR_INVALID_VALUE
+    assert L.hs_gemv(8, 8, B.HS_F32, B.hs_schedule(3, 2), FAKE, 8, FAKE, FAKE, None, 0, None) == \
+        B.HS_ERR_INVALID_VALUE
+    assert L.hs_gemv(0, 8, B.HS_F32, s, None, 8, None, None, None, 0, None) == B.HS_OK
+
+
+def test_backward_rejects():
+    L = B.lib()
+    s = B.hs_schedule(2, 0)
+    args = [8, 8, 8, B.HS_F32, s, FAKE, 8, FAKE, 8, FAKE, 8, FAKE, 8, FAKE, 8, FAKE, 1 << 30, None]
+    bad = list(args)
+    bad[9] = None                      # G missing
+    assert L.hs_gemm_backward(*bad) == B.HS_ERR_INVALID_VALUE
+    bad = list(args)
+    bad[16] = 8                        # workspace too small
+    assert L.hs_gemm_backward(*bad) == B.HS_ERR_WORKSPACE_TOO_SMALL
+    bad = list(args)
+    bad[12] = 4                        # ldda < k
+    assert L.hs_gemm_backward(*bad) == B.HS_ERR_INVALID_VALUE
+    both_null = list(args)
+    both_null[11] = None
+    both_null[13] = None
+    assert L.hs_gemm_backward(*both_null) == B.HS_OK   # nothing to do
+
+
+def test_empty_problems_need_nothing():
+    assert _gemm(m=0, A=None, C=None, ws=None, wsb=0) == B.HS_OK
+    assert _gemm(n=0, Bp=None, C=None, ws=None, wsb=0) == B.HS_OK
+
+
+def test_profile_end_without_begin():
+    assert B.lib().hs_profile_end(None, None) == B.HS_ERR_INVALID_VALUE
