@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--compare", default="f32", help="form timed beside the headline ('' to skip)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle baseline sample (0 to skip)")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run one plain 256 MiB device copy first (reference for HBM counters)")
     return ap.parse_args()
 
 
@@ -47,7 +49,14 @@ def step(hs, A, B, G, form, p, K):
     return C, dA, dB
 
 
+STORAGE = {"bf16": "bfloat16", "f16": "float16", "f64": "float64"}
+
+
 def run_form(hs, torch, A, B, G, form, p, K, steps, warmup):
+    if form in STORAGE:   # the 16-bit and FP64 forms take inputs of their own type
+        dt = getattr(torch, STORAGE[form])
+        A, B, G = A.to(dt), B.to(dt), G.to(dt)
+        torch.cuda.synchronize()
     for _ in range(warmup):
         step(hs, A, B, G, form, p, K)
     torch.cuda.synchronize()
@@ -67,15 +76,17 @@ def cpu_baseline(A64, B64, G64, target_s):
     from paper_cs_9809105_amd import inputs
     n = A64.shape[0]
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    # calibrate on 2 rows of each product, then size the sample to ~target_s
-    rows = inputs.sample_rows(n, 2, seed=7)
+    # calibrate on one row per core of each product, then size the sample
+    # (a multiple of the core count) to about target_s
+    cal = min(n, cores)
+    rows = inputs.sample_rows(n, cal, seed=7)
     t0 = time.perf_counter()
     oracle.gemm_rows(A64, B64, rows)
     oracle.grad_a_rows(G64, B64, rows)
     oracle.grad_b_rows(A64, G64, rows)
     t_cal = time.perf_counter() - t0
-    nrows = max(2, min(n, int(2 * target_s / max(t_cal, 1e-6))))
-    nrows = max(cores, (nrows // cores) * cores) if nrows >= cores else nrows
+    nrows = int(cal * target_s / max(t_cal, 1e-6))
+    nrows = max(cal, min(n, (nrows // cores) * cores))
     rows = inputs.sample_rows(n, nrows, seed=8)
     t0 = time.perf_counter()
     oracle.gemm_rows(A64, B64, rows)
@@ -111,6 +122,12 @@ def main():
     B64 = B.cpu().double().numpy()
     G64 = G.cpu().double().numpy()
     torch.cuda.synchronize()
+    if args.calib_copy:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     useful = 3 * 2.0 * n ** 3
     wall, kern_ms, launches = run_form(hs, torch, A, B, G, args.form, p, K, args.steps, args.warmup)

@@ -68,6 +68,14 @@ struct Plan {
     size_t off_a, off_b, off_w, total;
 };
 
+// Threads of the pack kernel: one per 16-byte unit; a K-major source is
+// walked in 8 x 8 (row, unit) blocks, so both counts round up to 8.
+int64_t pack_units(const OperandGeom &g, int kmajor) {
+    const int64_t nu = g.nch * (g.chunk_bytes / 16);
+    if (kmajor) return g.n_groups * g.p * ((nu + 7) / 8 * 8) * ((g.grp_rows + 7) / 8 * 8);
+    return g.n_groups * g.p * nu * g.grp_rows;
+}
+
 // Geometry of one product C[M,N] = X[M,Kd] Y[Kd,N] under schedule (p, K).
 hs_status make_plan(int64_t M, int64_t N, int64_t Kd, hs_dtype dt, hs_schedule s, Plan *P) {
     if (!form_info(dt, &P->f)) return HS_ERR_NOT_SUPPORTED;
@@ -102,6 +110,12 @@ hs_status make_plan(int64_t M, int64_t N, int64_t Kd, hs_dtype dt, hs_schedule s
 
     const int64_t nwg = (int64_t)p * a.GS * b.GS;
     if (nwg > std::numeric_limits<int32_t>::max()) return HS_ERR_NOT_SUPPORTED;
+    // the main kernel addresses each packed operand with 32-bit offsets
+    const int64_t kMaxPacked = (int64_t)0xFFFFFFF0;
+    if (a.piece_bytes * NP > kMaxPacked || b.piece_bytes * NP > kMaxPacked) return HS_ERR_NOT_SUPPORTED;
+    // 32-bit indexing of the pack kernel and of the stage counter
+    if (pack_units(a, 1) >= (int64_t)1 << 31 || pack_units(b, 1) >= (int64_t)1 << 31) return HS_ERR_NOT_SUPPORTED;
+    if ((int64_t)P->Kt * nch >= (int64_t)1 << 31) return HS_ERR_NOT_SUPPORTED;
 
     size_t off = 0;
     P->off_a = off; off = align_up(off + (size_t)(a.piece_bytes * NP));
@@ -128,6 +142,19 @@ struct Operand {
 
 hs_status launch_status(hipError_t e) { return e == hipSuccess ? HS_OK : HS_ERR_LAUNCH_FAILED; }
 
+// A K-major source may be read 16 bytes at a time when every unit's
+// elements are contiguous, aligned and either all inside or all outside
+// the matrix and its contraction block.
+int pack_vec_ok(const Plan &P, const Operand &X) {
+    if (!X.kmajor) return 0;
+    const int64_t ue = 16 / P.f.packed_esz;          // source elements per unit
+    const int64_t in = P.f.in_esz;
+    if (P.f.pack == PK_SPLIT3) {                     // 8 fp32 per unit (two loads)
+        return (X.ld % 4 == 0 && aligned(X.ptr, 16) && P.ga.S_k % 8 == 0 && P.Kd % 8 == 0) ? 1 : 0;
+    }
+    return (X.ld * in % 16 == 0 && aligned(X.ptr, 16) && P.ga.S_k % ue == 0 && P.Kd % ue == 0) ? 1 : 0;
+}
+
 // One product through the hyper-systolic path.  The plan must come from
 // make_plan with the same sizes; ws holds at least plan.total bytes.
 hs_status run_product(const Plan &P, const Operand &X, const Operand &Y, void *out, int64_t ldo,
@@ -139,18 +166,22 @@ hs_status run_product(const Plan &P, const Operand &X, const Operand &Y, void *o
 
     PackArgs pa{};
     pa.src = X.ptr; pa.ld = X.ld; pa.g = P.ga; pa.dst = w + P.off_a;
-    pa.total_units = P.ga.n_groups * P.ga.p * P.ga.nch * P.ga.grp_rows * (P.ga.chunk_bytes / 16);
+    pa.total_units = pack_units(P.ga, X.kmajor);
+    pa.vec = pack_vec_ok(P, X);
     hipError_t e = launch_pack(P.f.pack, X.kmajor, pa, stream);
     if (e != hipSuccess) return HS_ERR_LAUNCH_FAILED;
     PackArgs pb{};
     pb.src = Y.ptr; pb.ld = Y.ld; pb.g = P.gb; pb.dst = w + P.off_b;
-    pb.total_units = P.gb.n_groups * P.gb.p * P.gb.nch * P.gb.grp_rows * (P.gb.chunk_bytes / 16);
+    pb.total_units = pack_units(P.gb, Y.kmajor);
+    pb.vec = pack_vec_ok(P, Y);
     e = launch_pack(P.f.pack, Y.kmajor, pb, stream);
     if (e != hipSuccess) return HS_ERR_LAUNCH_FAILED;
 
     MainArgs m{};
     m.A = w + P.off_a; m.a_piece = P.ga.piece_bytes;
     m.B = w + P.off_b; m.b_piece = P.gb.piece_bytes;
+    m.a_bytes = P.ga.piece_bytes * P.ga.pieces;
+    m.b_bytes = P.gb.piece_bytes * P.gb.pieces;
     const bool partials = P.K > 1;
     m.out = partials ? (void *)(w + P.off_w) : out;
     m.ldo = partials ? P.N : ldo;
@@ -163,11 +194,11 @@ hs_status run_product(const Plan &P, const Operand &X, const Operand &Y, void *o
     if (g_prof) {
         if (hipEventCreate(&ev0) != hipSuccess || hipEventCreate(&ev1) != hipSuccess)
             return HS_ERR_LAUNCH_FAILED;
-        hipEventRecord(ev0, stream);
+        (void)hipEventRecord(ev0, stream);
     }
     e = launch_mm(P.f.fam, P.f.form, m, stream);
     if (g_prof) {
-        hipEventRecord(ev1, stream);
+        (void)hipEventRecord(ev1, stream);
         g_events.push_back({ev0, ev1});
     }
     if (e != hipSuccess) return HS_ERR_LAUNCH_FAILED;
@@ -315,11 +346,11 @@ hs_status hs_gemv(int64_t m, int64_t n, hs_dtype dtype, hs_schedule s,
     if (g_prof) {
         if (hipEventCreate(&ev0) != hipSuccess || hipEventCreate(&ev1) != hipSuccess)
             return HS_ERR_LAUNCH_FAILED;
-        hipEventRecord(ev0, st);
+        (void)hipEventRecord(ev0, st);
     }
     hipError_t e = launch_gemv(f64, g, st);
     if (g_prof) {
-        hipEventRecord(ev1, st);
+        (void)hipEventRecord(ev1, st);
         g_events.push_back({ev0, ev1});
     }
     return launch_status(e);
@@ -369,8 +400,8 @@ hs_status hs_profile_end(double *total_ms, int64_t *launches) {
             st = HS_ERR_LAUNCH_FAILED;
         tot += ms;
         ++n;
-        hipEventDestroy(pr.first);
-        hipEventDestroy(pr.second);
+        (void)hipEventDestroy(pr.first);
+        (void)hipEventDestroy(pr.second);
     }
     g_events.clear();
     if (total_ms) *total_ms = tot;

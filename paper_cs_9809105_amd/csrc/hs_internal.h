@@ -56,7 +56,8 @@ struct PackArgs {
     int64_t scale_piece_bytes;
     const float *tile_scale; // fp8 only: per 128x128 tile exponent info
     int64_t tiles_r, tiles_k;
-    int64_t total_units;
+    int64_t total_units;     // < 2^31
+    int vec;                 // K-major source: 16-byte vector loads are legal
 };
 
 struct MainArgs {
@@ -64,6 +65,7 @@ struct MainArgs {
     int64_t a_piece;         // bytes between pieces
     const uint8_t *B;        // packed travelling operand
     int64_t b_piece;
+    int64_t a_bytes, b_bytes; // total packed bytes (all pieces), each < 4 GiB
     const uint8_t *a_scale;  // fp8 only
     int64_t a_scale_piece;
     const uint8_t *b_scale;

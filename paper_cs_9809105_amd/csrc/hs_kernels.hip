@@ -33,6 +33,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));   // 16 bytes, a native vector
 
 // ---------------------------------------------------------------------------
 // number formats
@@ -55,27 +56,45 @@ template <> struct PackTraits<PK_F32> { typedef float S; static const int UE = 4
 template <> struct PackTraits<PK_B16> { typedef uint16_t S; static const int UE = 8; static const int ESZ = 2; static const int NP = 1; };
 template <> struct PackTraits<PK_SPLIT3> { typedef float S; static const int UE = 8; static const int ESZ = 2; static const int NP = 3; };
 
+// One thread makes one 16-byte unit of the packed image (for the split form,
+// the same unit of each of the three pieces).  Consecutive threads take
+// consecutive rows of one (group, block, chunk, plane), so the packed writes
+// are contiguous; for a row-major (MN-major) source the reads are contiguous
+// too, for a K-major source each thread reads its own 16-32 bytes of a row.
 template <int KIND, int KMAJOR>
 __global__ __launch_bounds__(256) void pack_kernel(PackArgs a) {
     typedef PackTraits<KIND> T;
     typedef typename T::S S;
     const OperandGeom &g = a.g;
-    const int64_t u = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (u >= a.total_units) return;
+    const uint32_t u = blockIdx.x * 256u + threadIdx.x;     // host: total_units < 2^31
+    if (u >= (uint32_t)a.total_units) return;
     const int KC = g.chunk_bytes / T::ESZ;      // elements per chunk row
-    const int UPR = g.chunk_bytes / 16;         // 16-byte units per chunk row
-    const int64_t nch = g.nch, p = g.p, gr = g.grp_rows;
-    int64_t t, rr, half, ch, kb, grp;
-    if (KMAJOR) {   // consecutive threads walk along the contraction of one row
-        half = u % UPR; t = u / UPR;
-        ch = t % nch;   t /= nch;
-        kb = t % p;     t /= p;
-        rr = t % gr;    grp = t / gr;
-    } else {        // consecutive threads walk along the rows
-        rr = u % gr;    t = u / gr;
+    const uint32_t UPR = (uint32_t)(g.chunk_bytes / 16);  // 16-byte planes per chunk row
+    const uint32_t nch = (uint32_t)g.nch, p = (uint32_t)g.p, gr = (uint32_t)g.grp_rows;
+    uint32_t t = u, rr, half, ch, kb, grp;
+    if (KMAJOR) {
+        // 8 x 8 blocks of (row, unit along the contraction): a wave reads 8
+        // rows x 8 consecutive units (128-256 contiguous bytes per row) and
+        // writes, per (chunk, plane), 8 consecutive rows (128 bytes).
+        const uint32_t nu = nch * UPR;                  // units along one block row
+        const uint32_t nkg = (nu + 7) / 8, nrg = (gr + 7) / 8;
+        const uint32_t uu = t % 8;  t /= 8;
+        const uint32_t rlo = t % 8; t /= 8;
+        const uint32_t kg = t % nkg; t /= nkg;
+        const uint32_t rhi = t % nrg; t /= nrg;
+        kb = t % p;
+        grp = t / p;
+        const uint32_t ku = kg * 8 + uu;
+        rr = rhi * 8 + rlo;
+        if (ku >= nu || rr >= gr) return;
+        ch = ku / UPR;
+        half = ku % UPR;
+    } else {
+        rr = t % gr;    t /= gr;
         half = t % UPR; t /= UPR;
         ch = t % nch;   t /= nch;
-        kb = t % p;     grp = t / p;
+        kb = t % p;
+        grp = t / p;
     }
     int64_t row;
     bool rvalid;
@@ -85,37 +104,62 @@ __global__ __launch_bounds__(256) void pack_kernel(PackArgs a) {
         row = stripe * g.S_r + within;
         rvalid = within < g.S_r && row < g.R;
     } else {
-        row = grp * gr + rr;
+        row = (int64_t)grp * gr + rr;
         rvalid = row < g.R;
     }
-    const int64_t kin0 = ch * KC + half * T::UE;
+    const int64_t kin0 = (int64_t)ch * KC + half * T::UE;
+    const int64_t kk0 = (int64_t)kb * g.S_k + kin0;
     const S *src = (const S *)a.src;
     float vals_f[T::UE];
     double vals_d[T::UE];
     uint16_t vals_h[T::UE];
+    if (KMAJOR && a.vec) {
+        // the unit's elements are contiguous, 16-byte aligned, all valid or all padding
+        const bool ok = rvalid && kin0 < g.S_k && kk0 < g.Kd;
+        const S *q = src + row * a.ld + kk0;
+        constexpr int SB = (int)sizeof(S);             // source element bytes
+        constexpr int NV = T::UE * SB / 16;            // 16-byte loads per unit
+        u32x4 w[NV];
 #pragma unroll
-    for (int e = 0; e < T::UE; ++e) {
-        const int64_t kin = kin0 + e;
-        const int64_t kk = kb * g.S_k + kin;
-        const bool ok = rvalid && kin < g.S_k && kk < g.Kd;
-        const int64_t idx = KMAJOR ? row * a.ld + kk : kk * a.ld + row;
-        if constexpr (KIND == PK_F64) vals_d[e] = ok ? (double)src[idx] : 0.0;
-        else if constexpr (KIND == PK_B16) vals_h[e] = ok ? (uint16_t)src[idx] : (uint16_t)0;
-        else vals_f[e] = ok ? (float)src[idx] : 0.0f;
+        for (int i = 0; i < NV; ++i) w[i] = ok ? *(const u32x4 *)(q + i * (16 / SB)) : u32x4{0, 0, 0, 0};
+#pragma unroll
+        for (int e = 0; e < T::UE; ++e) {
+            const int byte = e * SB;
+            const uint32_t word = w[byte / 16][(byte % 16) / 4];
+            if constexpr (KIND == PK_F64) {
+                vals_d[e] = __hiloint2double((int)w[byte / 16][(byte % 16) / 4 + 1], (int)word);
+            } else if constexpr (KIND == PK_B16) {
+                vals_h[e] = (uint16_t)(word >> ((byte % 4) * 8));
+            } else {
+                vals_f[e] = __uint_as_float(word);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < T::UE; ++e) {
+            const int64_t kin = kin0 + e;
+            const int64_t kk = kk0 + e;
+            const bool ok = rvalid && kin < g.S_k && kk < g.Kd;
+            const int64_t idx = KMAJOR ? row * a.ld + kk : kk * a.ld + row;
+            if constexpr (KIND == PK_F64) vals_d[e] = ok ? (double)src[idx] : 0.0;
+            else if constexpr (KIND == PK_B16) vals_h[e] = ok ? (uint16_t)src[idx] : (uint16_t)0;
+            else vals_f[e] = ok ? (float)src[idx] : 0.0f;
+        }
     }
-    const int64_t off = (((grp * p + kb) * nch + ch) * gr + rr) * g.chunk_bytes + half * 16;
+    // chunk = UPR planes of 16 bytes per row: [plane][row][16 bytes]
+    const int64_t off = (((int64_t)grp * p + kb) * nch + ch) * gr * g.chunk_bytes + ((int64_t)half * gr + rr) * 16;
     uint8_t *dst = (uint8_t *)a.dst + off;
     if constexpr (KIND == PK_F64) {
         *(double2 *)dst = make_double2(vals_d[0], vals_d[1]);
     } else if constexpr (KIND == PK_F32) {
         *(float4 *)dst = make_float4(vals_f[0], vals_f[1], vals_f[2], vals_f[3]);
     } else if constexpr (KIND == PK_B16) {
-        uint4 w;
-        w.x = vals_h[0] | ((uint32_t)vals_h[1] << 16);
-        w.y = vals_h[2] | ((uint32_t)vals_h[3] << 16);
-        w.z = vals_h[4] | ((uint32_t)vals_h[5] << 16);
-        w.w = vals_h[6] | ((uint32_t)vals_h[7] << 16);
-        *(uint4 *)dst = w;
+        u32x4 w;
+        w[0] = vals_h[0] | ((uint32_t)vals_h[1] << 16);
+        w[1] = vals_h[2] | ((uint32_t)vals_h[3] << 16);
+        w[2] = vals_h[4] | ((uint32_t)vals_h[5] << 16);
+        w[3] = vals_h[6] | ((uint32_t)vals_h[7] << 16);
+        *(u32x4 *)dst = w;
     } else {   // PK_SPLIT3: a0 = bf16(a), a1 = bf16(a - a0), a2 = bf16(a - a0 - a1)
         uint16_t p0[8], p1[8], p2[8];
 #pragma unroll
@@ -131,12 +175,12 @@ __global__ __launch_bounds__(256) void pack_kernel(PackArgs a) {
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
             const uint16_t *h = pc[q];
-            uint4 w;
-            w.x = h[0] | ((uint32_t)h[1] << 16);
-            w.y = h[2] | ((uint32_t)h[3] << 16);
-            w.z = h[4] | ((uint32_t)h[5] << 16);
-            w.w = h[6] | ((uint32_t)h[7] << 16);
-            *(uint4 *)(dst + q * g.piece_bytes) = w;
+            u32x4 w;
+            w[0] = h[0] | ((uint32_t)h[1] << 16);
+            w[1] = h[2] | ((uint32_t)h[3] << 16);
+            w[2] = h[4] | ((uint32_t)h[5] << 16);
+            w[3] = h[6] | ((uint32_t)h[7] << 16);
+            *(u32x4 *)(dst + q * g.piece_bytes) = w;
         }
     }
 }
@@ -156,25 +200,28 @@ template <> struct Mfma<FAM_F32> { static const int T = 32; typedef f32x16 Acc; 
 template <> struct Mfma<FAM_BF16> { static const int T = 32; typedef f32x16 Acc; };
 template <> struct Mfma<FAM_F16> { static const int T = 32; typedef f32x16 Acc; };
 
-template <int FAM, int FORM, int BM, int BN, int CPS>
+template <int FAM, int FORM, int BM, int BN, int CPS, int WAVES>
 struct MmCfg {
     static const int NP = Form<FORM>::NP;
+    static const int NT = 64 * WAVES;                   // threads per workgroup
     static const int CB = 32;                           // bytes per chunk row
     static const int A_STAGE = NP * CPS * BM * CB;      // LDS bytes per stage
     static const int B_STAGE = NP * CPS * BN * CB;
-    static const int UA = NP * CPS * BM * 2 / 256;      // 16-byte loads per thread
-    static const int UB = NP * CPS * BN * 2 / 256;
-    static const int WM = BM / 2, WN = BN / 2;          // 2 x 2 waves
+    static const int UA = NP * CPS * BM * 2 / NT;       // 16-byte loads per thread
+    static const int UB = NP * CPS * BN * 2 / NT;
+    static_assert(UA * NT == NP * CPS * BM * 2 && UB * NT == NP * CPS * BN * 2, "tile/threads");
+    static const int WM = BM / 2, WN = BN / (WAVES / 2); // waves: 2 along rows, WAVES/2 along columns
     static const int MT = Mfma<FAM>::T;
     static const int TM = WM / MT, TN = WN / MT;
-    static const int LDS = 2 * (A_STAGE + B_STAGE);
+    static const int STAGE = A_STAGE + B_STAGE;         // one slot of the LDS ring
+    static const int LPS = UA + UB;                     // DMA loads per thread per stage
 };
 
 // One pipeline stage of block products from LDS: for every chunk of the
 // stage, the wave's MFMA tiles accumulate A_rows x B_cols.
-template <int FAM, int FORM, int BM, int BN, int CPS, typename AccArr>
+template <int FAM, int FORM, int BM, int BN, int CPS, int WAVES, typename AccArr>
 DEVI void mm_compute(AccArr &acc, const uint8_t *Ab, const uint8_t *Bb, int lane, int wm, int wn) {
-    typedef MmCfg<FAM, FORM, BM, BN, CPS> C;
+    typedef MmCfg<FAM, FORM, BM, BN, CPS, WAVES> C;
 #pragma unroll
     for (int c = 0; c < CPS; ++c) {
         if constexpr (FAM == FAM_F64) {
@@ -182,10 +229,10 @@ DEVI void mm_compute(AccArr &acc, const uint8_t *Ab, const uint8_t *Bb, int lane
             double av[C::TM], bv[C::TN];
 #pragma unroll
             for (int mi = 0; mi < C::TM; ++mi)
-                av[mi] = *(const double *)(Ab + (c * BM + wm * C::WM + mi * 16 + r16) * C::CB + g * 8);
+                av[mi] = *(const double *)(Ab + (c * 2 + (g >> 1)) * BM * 16 + (wm * C::WM + mi * 16 + r16) * 16 + (g & 1) * 8);
 #pragma unroll
             for (int ni = 0; ni < C::TN; ++ni)
-                bv[ni] = *(const double *)(Bb + (c * BN + wn * C::WN + ni * 16 + r16) * C::CB + g * 8);
+                bv[ni] = *(const double *)(Bb + (c * 2 + (g >> 1)) * BN * 16 + (wn * C::WN + ni * 16 + r16) * 16 + (g & 1) * 8);
 #pragma unroll
             for (int mi = 0; mi < C::TM; ++mi)
 #pragma unroll
@@ -193,35 +240,36 @@ DEVI void mm_compute(AccArr &acc, const uint8_t *Ab, const uint8_t *Bb, int lane
                     acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[mi], bv[ni], acc[mi][ni], 0, 0, 0);
         } else {
             const int r32 = lane & 31, g = lane >> 5;
-            uint4 av[C::NP][C::TM], bv[C::NP][C::TN];
+            // all B fragments of the chunk, then one row tile of A at a time
+            u32x4 bv[C::NP][C::TN];
 #pragma unroll
-            for (int P = 0; P < C::NP; ++P) {
-#pragma unroll
-                for (int mi = 0; mi < C::TM; ++mi)
-                    av[P][mi] = *(const uint4 *)(Ab + ((P * CPS + c) * BM + wm * C::WM + mi * 32 + r32) * C::CB + g * 16);
+            for (int P = 0; P < C::NP; ++P)
 #pragma unroll
                 for (int ni = 0; ni < C::TN; ++ni)
-                    bv[P][ni] = *(const uint4 *)(Bb + ((P * CPS + c) * BN + wn * C::WN + ni * 32 + r32) * C::CB + g * 16);
-            }
+                    bv[P][ni] = *(const u32x4 *)(Bb + (P * CPS + c) * BN * C::CB + g * BN * 16 +
+                                                 (wn * C::WN + ni * 32 + r32) * 16);
 #pragma unroll
-            for (int mi = 0; mi < C::TM; ++mi)
+            for (int mi = 0; mi < C::TM; ++mi) {
+                u32x4 av[C::NP];
+#pragma unroll
+                for (int P = 0; P < C::NP; ++P)
+                    av[P] = *(const u32x4 *)(Ab + (P * CPS + c) * BM * C::CB + g * BM * 16 +
+                                             (wm * C::WM + mi * 32 + r32) * 16);
 #pragma unroll
                 for (int ni = 0; ni < C::TN; ++ni) {
                     if constexpr (FAM == FAM_F32) {
                         // lane group g holds contraction elements 4g..4g+3 of
                         // the chunk; MFMA t takes element t of A and B alike
-                        const float4 x = __builtin_bit_cast(float4, av[0][mi]);
-                        const float4 y = __builtin_bit_cast(float4, bv[0][ni]);
-                        acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x2f32(x.x, y.x, acc[mi][ni], 0, 0, 0);
-                        acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x2f32(x.y, y.y, acc[mi][ni], 0, 0, 0);
-                        acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x2f32(x.z, y.z, acc[mi][ni], 0, 0, 0);
-                        acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x2f32(x.w, y.w, acc[mi][ni], 0, 0, 0);
+#pragma unroll
+                        for (int t = 0; t < 4; ++t)
+                            acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x2f32(
+                                __uint_as_float(av[0][t]), __uint_as_float(bv[0][ni][t]), acc[mi][ni], 0, 0, 0);
                     } else if constexpr (FAM == FAM_F16) {
                         acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
-                            __builtin_bit_cast(f16x8, av[0][mi]), __builtin_bit_cast(f16x8, bv[0][ni]), acc[mi][ni], 0, 0, 0);
+                            __builtin_bit_cast(f16x8, av[0]), __builtin_bit_cast(f16x8, bv[0][ni]), acc[mi][ni], 0, 0, 0);
                     } else if constexpr (FORM == 0) {
                         acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                            __builtin_bit_cast(bf16x8, av[0][mi]), __builtin_bit_cast(bf16x8, bv[0][ni]), acc[mi][ni], 0, 0, 0);
+                            __builtin_bit_cast(bf16x8, av[0]), __builtin_bit_cast(bf16x8, bv[0][ni]), acc[mi][ni], 0, 0, 0);
                     } else {
                         // a2 b0, a1 b1, a0 b2, a1 b0, a0 b1, a0 b0: smallest first
 #pragma unroll
@@ -229,41 +277,53 @@ DEVI void mm_compute(AccArr &acc, const uint8_t *Ab, const uint8_t *Bb, int lane
                             const int pa = q < 3 ? 2 - q : (q == 3 ? 1 : 0);
                             const int pb = q < 3 ? q : (q == 4 ? 1 : 0);
                             acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                                __builtin_bit_cast(bf16x8, av[pa][mi]), __builtin_bit_cast(bf16x8, bv[pb][ni]), acc[mi][ni], 0, 0, 0);
+                                __builtin_bit_cast(bf16x8, av[pa]), __builtin_bit_cast(bf16x8, bv[pb][ni]), acc[mi][ni], 0, 0, 0);
                         }
                     }
                 }
+            }
         }
     }
 }
 
-// Global -> registers for one stage: the travelling block kb held at step j
-// and the K static blocks of the same contraction range.
-template <int UA, int UB>
-DEVI void mm_load(uint4 (&ra)[UA], uint4 (&rb)[UB], const uint8_t *A, const uint8_t *B,
-                  const int64_t (&a_off)[UA], const int64_t (&b_off)[UB], int64_t ach, int64_t bch) {
-#pragma unroll
-    for (int q = 0; q < UA; ++q) ra[q] = *(const uint4 *)(A + (a_off[q] >= 0 ? a_off[q] + ach : 0));
-#pragma unroll
-    for (int q = 0; q < UB; ++q) rb[q] = *(const uint4 *)(B + b_off[q] + bch);
+// Buffer resource over a packed operand (raw buffer, byte addressed; the
+// third dword is the gfx9 default format word).
+DEVI __amdgpu_buffer_rsrc_t packed_rsrc(const uint8_t *base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, (int)bytes, 0x00020000);
 }
 
+// Global -> registers for one stage: 16-byte buffer loads of the K static
+// blocks and of the travelling block.  The per-thread part of each address
+// is a constant 32-bit offset; the stage part is wave-uniform (SGPR).
 template <int UA, int UB>
-DEVI void mm_store(const uint4 (&ra)[UA], const uint4 (&rb)[UB], uint8_t *As, uint8_t *Bs, int tid) {
+DEVI void stage_load(u32x4 (&r)[UA + UB], __amdgpu_buffer_rsrc_t ra, __amdgpu_buffer_rsrc_t rb,
+                     const uint32_t (&a_off)[UA], const uint32_t (&b_off)[UB], uint32_t ach, uint32_t bch) {
 #pragma unroll
-    for (int q = 0; q < UA; ++q) *(uint4 *)(As + (tid + 256 * q) * 16) = ra[q];
+    for (int q = 0; q < UA; ++q)
+        r[q] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(ra, (int)a_off[q], (int)ach, 0));
 #pragma unroll
-    for (int q = 0; q < UB; ++q) *(uint4 *)(Bs + (tid + 256 * q) * 16) = rb[q];
+    for (int q = 0; q < UB; ++q)
+        r[UA + q] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rb, (int)b_off[q], (int)bch, 0));
 }
 
-template <int FAM, int FORM, int BM, int BN, int CPS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+// Registers -> LDS slot.  The LDS image of a stage is
+// [slab = (piece, chunk)][plane][row][16 bytes]: unit ui = tid + NT q lands
+// at ui * 16, so consecutive lanes write consecutive 16 bytes, and the 32
+// lanes of an MFMA lane group later read 512 contiguous bytes of one plane.
+template <int UA, int UB, int A_STAGE, int NT>
+DEVI void stage_store(const u32x4 (&r)[UA + UB], uint8_t *slot, int tid) {
+#pragma unroll
+    for (int q = 0; q < UA; ++q) *(u32x4 *)(slot + (tid + NT * q) * 16) = r[q];
+#pragma unroll
+    for (int q = 0; q < UB; ++q) *(u32x4 *)(slot + A_STAGE + (tid + NT * q) * 16) = r[UA + q];
+}
+
+template <int FAM, int FORM, int BM, int BN, int CPS, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(WAVES / 4, WAVES / 4)))
 void mm_kernel(MainArgs a) {
-    typedef MmCfg<FAM, FORM, BM, BN, CPS> C;
+    typedef MmCfg<FAM, FORM, BM, BN, CPS, WAVES> C;
     typedef typename Mfma<FAM>::Acc Acc;
-    extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
-    uint8_t *As = smem;
-    uint8_t *Bs = smem + 2 * C::A_STAGE;
+    extern __shared__ __attribute__((aligned(16))) uint8_t ring[];   // 2 * C::STAGE bytes
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -279,41 +339,57 @@ void mm_kernel(MainArgs a) {
 
     const int p = a.p, K = a.K, MS = a.MS;
     const int64_t nch = a.nch;
-    const int64_t SPB = nch / CPS;            // stages per contraction block
-    const int64_t nstages = (int64_t)a.Kt * SPB;
+    const int spb = (int)(nch / CPS);                   // stages per contraction block
+    const int nstages = a.Kt * spb;                     // host keeps this below 2^31
 
     // per-thread load descriptors: byte offsets that do not depend on the
     // step (group of the static operand, row, half-row, piece, chunk).  Units
     // past the K groups (only when K * MS < BM) re-read offset 0: their tile
-    // rows are never stored.
-    int64_t a_off[C::UA];
+    // rows are never stored.  The host guarantees every packed operand is
+    // below 4 GiB, so 32-bit offsets address it.
+    uint32_t a_off[C::UA];
 #pragma unroll
     for (int q = 0; q < C::UA; ++q) {
-        const int ui = tid + 256 * q;
+        const int ui = tid + C::NT * q;              // unit: [slab][plane][row]
         const int slab = ui / (BM * 2);
         const int within = ui % (BM * 2);
-        const int rho = within >> 1, half = within & 1;
+        const int half = within / BM, rho = within % BM;
         const int P = slab / CPS, c = slab % CPS;
         const int l = rho / MS, i = rho % MS;
         const int64_t grp = (int64_t)((v - l + p) % p) * a.GS + msub;
-        a_off[q] = l < K ? (int64_t)P * a.a_piece + grp * (int64_t)p * nch * MS * C::CB +
-                               (int64_t)c * MS * C::CB + (int64_t)i * C::CB + half * 16
-                         : (int64_t)-1;
+        a_off[q] = l < K ? (uint32_t)((int64_t)P * a.a_piece + grp * (int64_t)p * nch * MS * C::CB +
+                                      (int64_t)c * MS * C::CB + (int64_t)(half * MS + i) * 16)
+                         : 0u;
     }
-    int64_t b_off[C::UB];
+    uint32_t b_off[C::UB];
 #pragma unroll
     for (int q = 0; q < C::UB; ++q) {
-        const int ui = tid + 256 * q;
+        const int ui = tid + C::NT * q;
         const int slab = ui / (BN * 2);
         const int within = ui % (BN * 2);
         const int P = slab / CPS, c = slab % CPS;
-        b_off[q] = (int64_t)P * a.b_piece + ntile * (int64_t)p * nch * BN * C::CB +
-                   (int64_t)c * BN * C::CB + (int64_t)within * 16;
+        b_off[q] = (uint32_t)((int64_t)P * a.b_piece + ntile * (int64_t)p * nch * BN * C::CB +
+                              (int64_t)c * BN * C::CB + (int64_t)within * 16);
     }
-    // Stage position: step j holds travelling block kb = (v + jK) mod p
-    // (base A = (0, K, .., K)); cs counts the stages inside that block.
-    int kb = v, cs = 0;
-    const int spb = (int)SPB;
+    const __amdgpu_buffer_rsrc_t rsA = packed_rsrc(a.A, (uint32_t)a.a_bytes);
+    const __amdgpu_buffer_rsrc_t rsB = packed_rsrc(a.B, (uint32_t)a.b_bytes);
+
+    // Position of the next stage to fetch: step j holds travelling block
+    // kb = (v + jK) mod p (base A = (0, K, .., K)); cs counts the stages
+    // inside that block.  Past the last stage the position stays put, so the
+    // surplus fetches re-read the last stage (never used).
+    int kb = v, cs = 0, fetched = 0;
+    const uint32_t a_stage = (uint32_t)(MS * C::CB), b_stage = (uint32_t)(BN * C::CB);
+    auto fetch_offsets = [&](uint32_t &ach, uint32_t &bch) {
+        const uint32_t ch = (uint32_t)kb * (uint32_t)nch + (uint32_t)(cs * CPS);
+        ach = ch * a_stage;
+        bch = ch * b_stage;
+        if (++fetched < nstages && ++cs == spb) {   // next step: shift by K along the ring
+            cs = 0;
+            kb += K;
+            if (kb >= p) kb -= p;
+        }
+    };
 
     Acc acc[C::TM][C::TN];
 #pragma unroll
@@ -321,31 +397,58 @@ void mm_kernel(MainArgs a) {
 #pragma unroll
         for (int ni = 0; ni < C::TN; ++ni) acc[mi][ni] = Acc{};
 
-    uint4 ra[C::UA], rb[C::UB];
-    {
-        const int64_t ch = (int64_t)kb * nch + cs * CPS;
-        mm_load<C::UA, C::UB>(ra, rb, a.A, a.B, a_off, b_off, ch * MS * C::CB, ch * BN * C::CB);
-        mm_store<C::UA, C::UB>(ra, rb, As, Bs, tid);
-    }
+    // Pipeline: the global loads for stage s + 2 are issued at the top of
+    // stage s into one of two register sets and land in LDS at the end of
+    // stage s + 1, so each fetch has two stages of MFMA work to arrive.
+    // LDS holds two slots: stage s is read from slot s % 2 while stage s + 1
+    // is written into the other one.
+    u32x4 r0[C::LPS], r1[C::LPS];
+    uint32_t ach, bch;
+    fetch_offsets(ach, bch);
+    stage_load<C::UA, C::UB>(r0, rsA, rsB, a_off, b_off, ach, bch);
+    fetch_offsets(ach, bch);
+    stage_load<C::UA, C::UB>(r1, rsA, rsB, a_off, b_off, ach, bch);
+    stage_store<C::UA, C::UB, C::A_STAGE, C::NT>(r0, ring, tid);
     __syncthreads();
-
-    for (int64_t s = 0; s + 1 < nstages; ++s) {
-        const int buf = (int)(s & 1);
-        if (++cs == spb) {           // next step: shift by K along the ring
-            cs = 0;
-            kb += K;
-            if (kb >= p) kb -= p;
-        }
-        const int64_t ch = (int64_t)kb * nch + cs * CPS;
-        mm_load<C::UA, C::UB>(ra, rb, a.A, a.B, a_off, b_off, ch * MS * C::CB, ch * BN * C::CB);
-        mm_compute<FAM, FORM, BM, BN, CPS>(acc, As + buf * C::A_STAGE, Bs + buf * C::B_STAGE, lane, wm, wn);
-        mm_store<C::UA, C::UB>(ra, rb, As + (buf ^ 1) * C::A_STAGE, Bs + (buf ^ 1) * C::B_STAGE, tid);
-        __syncthreads();
+#ifndef HS_STORE_FIRST
+#define HS_STORE_FIRST 1
+#endif
+#if HS_STORE_FIRST
+    // The LDS image of stage s + 1 is written at the top of stage s (its
+    // loads were issued a stage earlier), so the writes overlap the MFMAs
+    // of stage s and the barrier only closes the stage.
+#define HS_PIPE_STEP(RLOAD, RSTORE)                                                            \
+    {                                                                                          \
+        const int slot = (int)(s & 1);                                                         \
+        fetch_offsets(ach, bch);                                                               \
+        stage_load<C::UA, C::UB>(RLOAD, rsA, rsB, a_off, b_off, ach, bch);                     \
+        stage_store<C::UA, C::UB, C::A_STAGE, C::NT>(RSTORE, ring + (slot ^ 1) * C::STAGE, tid); \
+        __builtin_amdgcn_sched_barrier(0);                                                     \
+        mm_compute<FAM, FORM, BM, BN, CPS, WAVES>(acc, ring + slot * C::STAGE,                 \
+                                           ring + slot * C::STAGE + C::A_STAGE, lane, wm, wn); \
+        __syncthreads();                                                                       \
+        if (++s >= nstages) break;                                                             \
     }
-    {
-        const int buf = (int)((nstages - 1) & 1);
-        mm_compute<FAM, FORM, BM, BN, CPS>(acc, As + buf * C::A_STAGE, Bs + buf * C::B_STAGE, lane, wm, wn);
+#else
+#define HS_PIPE_STEP(RLOAD, RSTORE)                                                            \
+    {                                                                                          \
+        const int slot = (int)(s & 1);                                                         \
+        fetch_offsets(ach, bch);                                                               \
+        stage_load<C::UA, C::UB>(RLOAD, rsA, rsB, a_off, b_off, ach, bch);                     \
+        __builtin_amdgcn_sched_barrier(0);                                                     \
+        mm_compute<FAM, FORM, BM, BN, CPS, WAVES>(acc, ring + slot * C::STAGE,                 \
+                                           ring + slot * C::STAGE + C::A_STAGE, lane, wm, wn); \
+        __builtin_amdgcn_sched_barrier(0);                                                     \
+        stage_store<C::UA, C::UB, C::A_STAGE, C::NT>(RSTORE, ring + (slot ^ 1) * C::STAGE, tid); \
+        __syncthreads();                                                                       \
+        if (++s >= nstages) break;                                                             \
     }
+#endif
+    for (int s = 0; s < nstages;) {
+        HS_PIPE_STEP(r0, r1)
+        HS_PIPE_STEP(r1, r0)
+    }
+#undef HS_PIPE_STEP
 
     // epilogue: partial l of the tile row rho goes to output stripe (v - l).
     // One tile row at a time (row index computed once, then its columns).
@@ -382,7 +485,10 @@ void mm_kernel(MainArgs a) {
 // ---------------------------------------------------------------------------
 // back-shift and accumulation (fixed order, FP64)
 // ---------------------------------------------------------------------------
-template <typename PT, typename OT>
+// Each thread sums 4 consecutive columns of one row over the K partial
+// planes, c^{K-1} first: S = c^l + S for l = K-2 .. 0 (back-shift order).
+// VEC: N % 4 == 0 (16-byte partial loads); VST: 16-byte stores into C legal.
+template <typename PT, typename OT, int VEC, int VST>
 __global__ __launch_bounds__(256) void backshift_kernel(const PT *W, int64_t plane, int K,
                                                         int64_t M, int64_t N, OT *Cout, int64_t ldc) {
     const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -390,19 +496,31 @@ __global__ __launch_bounds__(256) void backshift_kernel(const PT *W, int64_t pla
     if (idx >= M * n4) return;
     const int64_t row = idx / n4, c0 = (idx % n4) * 4;
     const int cnt = (int)((N - c0) < 4 ? (N - c0) : 4);
-    double s[4];
-    const PT *w = W + (int64_t)(K - 1) * plane + row * N + c0;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) s[e] = e < cnt ? (double)w[e] : 0.0;
-    for (int l = K - 2; l >= 0; --l) {       // c^l + (c^{l+1} + ...)
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int l = K - 1; l >= 0; --l) {
         const PT *wl = W + (int64_t)l * plane + row * N + c0;
+        PT x[4];
+        if constexpr (VEC && sizeof(PT) == 4) {
+            const float4 v = *(const float4 *)wl;
+            x[0] = v.x; x[1] = v.y; x[2] = v.z; x[3] = v.w;
+        } else if constexpr (VEC) {
+            const double2 v0 = *(const double2 *)wl, v1 = *(const double2 *)(wl + 2);
+            x[0] = v0.x; x[1] = v0.y; x[2] = v1.x; x[3] = v1.y;
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) x[e] = e < cnt ? wl[e] : (PT)0;
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) s[e] = (l == K - 1) ? (double)x[e] : (double)x[e] + s[e];
+    }
+    OT *c = Cout + row * ldc + c0;
+    if constexpr (VST && sizeof(OT) == 4) {
+        *(float4 *)c = make_float4((float)s[0], (float)s[1], (float)s[2], (float)s[3]);
+    } else {
 #pragma unroll
         for (int e = 0; e < 4; ++e)
-            if (e < cnt) s[e] = (double)wl[e] + s[e];
+            if (e < cnt) c[e] = (OT)s[e];
     }
-#pragma unroll
-    for (int e = 0; e < 4; ++e)
-        if (e < cnt) Cout[row * ldc + c0 + e] = (OT)s[e];
 }
 
 template <typename OT>
@@ -485,18 +603,18 @@ hipError_t launch_pack(int kind, int kmajor, const PackArgs &a, hipStream_t st) 
     return hipGetLastError();
 }
 
-template <int FAM, int FORM, int BM, int BN, int CPS>
+template <int FAM, int FORM, int BM, int BN, int CPS, int WAVES>
 static hipError_t launch_mm_t(const MainArgs &a, hipStream_t st) {
-    typedef MmCfg<FAM, FORM, BM, BN, CPS> C;
+    typedef MmCfg<FAM, FORM, BM, BN, CPS, WAVES> C;
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void *)mm_kernel<FAM, FORM, BM, BN, CPS>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, C::LDS);
+        hipError_t e = hipFuncSetAttribute((const void *)mm_kernel<FAM, FORM, BM, BN, CPS, WAVES>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 2 * C::STAGE);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
     const int64_t nwg = (int64_t)a.p * a.GS * a.n_ntiles;
-    hipLaunchKernelGGL((mm_kernel<FAM, FORM, BM, BN, CPS>), dim3((unsigned)nwg), dim3(256), C::LDS, st, a);
+    hipLaunchKernelGGL((mm_kernel<FAM, FORM, BM, BN, CPS, WAVES>), dim3((unsigned)nwg), dim3(C::NT), 2 * C::STAGE, st, a);
     return hipGetLastError();
 }
 
@@ -511,11 +629,20 @@ int mm_chunks_per_stage(int fam, int form) {
 }
 
 hipError_t launch_mm(int fam, int form, const MainArgs &a, hipStream_t st) {
-    if (fam == FAM_F64) return launch_mm_t<FAM_F64, 0, 64, 64, 4>(a, st);
-    if (fam == FAM_F32) return launch_mm_t<FAM_F32, 0, 256, 256, 2>(a, st);
-    if (fam == FAM_F16) return launch_mm_t<FAM_F16, 0, 256, 256, 2>(a, st);
-    if (fam == FAM_BF16 && form == 0) return launch_mm_t<FAM_BF16, 0, 256, 256, 2>(a, st);
-    if (fam == FAM_BF16 && form == 1) return launch_mm_t<FAM_BF16, 1, 256, 256, 1>(a, st);
+#ifndef HS_WAVES_F32
+#define HS_WAVES_F32 8
+#endif
+#ifndef HS_WAVES_B16
+#define HS_WAVES_B16 8
+#endif
+#ifndef HS_WAVES_SPLIT
+#define HS_WAVES_SPLIT 8
+#endif
+    if (fam == FAM_F64) return launch_mm_t<FAM_F64, 0, 64, 64, 4, 4>(a, st);
+    if (fam == FAM_F32) return launch_mm_t<FAM_F32, 0, 256, 256, 2, HS_WAVES_F32>(a, st);
+    if (fam == FAM_F16) return launch_mm_t<FAM_F16, 0, 256, 256, 2, HS_WAVES_B16>(a, st);
+    if (fam == FAM_BF16 && form == 0) return launch_mm_t<FAM_BF16, 0, 256, 256, 2, HS_WAVES_B16>(a, st);
+    if (fam == FAM_BF16 && form == 1) return launch_mm_t<FAM_BF16, 1, 256, 256, 1, HS_WAVES_SPLIT>(a, st);
     return hipErrorInvalidValue;
 }
 
@@ -523,12 +650,22 @@ hipError_t launch_backshift(int f64, const void *W, int64_t plane, int K, int64_
                             void *Cout, int64_t ldc, hipStream_t st) {
     const int64_t work = M * ((N + 3) / 4);
     if (work == 0) return hipSuccess;
-    if (f64)
-        hipLaunchKernelGGL((backshift_kernel<double, double>), dim3(nblocks(work)), dim3(256), 0, st,
-                           (const double *)W, plane, K, M, N, (double *)Cout, ldc);
-    else
-        hipLaunchKernelGGL((backshift_kernel<float, float>), dim3(nblocks(work)), dim3(256), 0, st,
-                           (const float *)W, plane, K, M, N, (float *)Cout, ldc);
+    const bool vec = N % 4 == 0;
+    const bool vst = vec && ldc % 4 == 0 && ((uintptr_t)Cout % 16) == 0;
+    const dim3 grid(nblocks(work)), block(256);
+    if (f64) {
+        if (vec) hipLaunchKernelGGL((backshift_kernel<double, double, 1, 0>), grid, block, 0, st,
+                                    (const double *)W, plane, K, M, N, (double *)Cout, ldc);
+        else hipLaunchKernelGGL((backshift_kernel<double, double, 0, 0>), grid, block, 0, st,
+                                (const double *)W, plane, K, M, N, (double *)Cout, ldc);
+    } else {
+        if (vst) hipLaunchKernelGGL((backshift_kernel<float, float, 1, 1>), grid, block, 0, st,
+                                    (const float *)W, plane, K, M, N, (float *)Cout, ldc);
+        else if (vec) hipLaunchKernelGGL((backshift_kernel<float, float, 1, 0>), grid, block, 0, st,
+                                         (const float *)W, plane, K, M, N, (float *)Cout, ldc);
+        else hipLaunchKernelGGL((backshift_kernel<float, float, 0, 0>), grid, block, 0, st,
+                                (const float *)W, plane, K, M, N, (float *)Cout, ldc);
+    }
     return hipGetLastError();
 }
 
