@@ -22,8 +22,9 @@ sys.path.insert(0, ROOT)
 PEAK = {  # MI355X published dense peaks
     "bf16": 2516.6, "f16": 2516.6, "fp8": 5033.2, "f32": 157.3, "f64": 78.6, "hbm_gbs": 8000.0,
 }
-MFMA_PRODUCTS = {"split3_bf16": 6, "bf16": 1, "f16": 1, "f32": 1, "f64": 1}
-MFMA_PEAK_KEY = {"split3_bf16": "bf16", "bf16": "bf16", "f16": "f16", "f32": "f32", "f64": "f64"}
+MFMA_PRODUCTS = {"split3_bf16": 6, "bf16": 1, "f16": 1, "f32": 1, "f64": 1, "fp8_e4m3": 1, "fp8_e4m3_r1": 3}
+MFMA_PEAK_KEY = {"split3_bf16": "bf16", "bf16": "bf16", "f16": "f16", "f32": "f32", "f64": "f64",
+                 "fp8_e4m3": "fp8", "fp8_e4m3_r1": "fp8"}
 
 
 def parse():
@@ -31,7 +32,11 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--n", type=int, default=8192)
+    ap.add_argument("--n", type=int, default=8192, help="square size (default workload)")
+    ap.add_argument("--shape", default="",
+                    help="M,Kd,N for a rectangular workload, e.g. 16384,8192,16384 (overrides --n)")
+    ap.add_argument("--inputs", default="rowscaled", choices=["rowscaled", "uniform"],
+                    help="rowscaled: N(0,1) with log-uniform row scales; uniform: U[-1,1]")
     ap.add_argument("--p", type=int, default=64)
     ap.add_argument("--K", type=int, default=2)
     ap.add_argument("--form", default="split3_bf16")
@@ -74,29 +79,33 @@ def cpu_baseline(A64, B64, G64, target_s):
     """The FP64 oracle on sampled rows of C, dA and dB (bounded sample)."""
     import oracle
     from paper_cs_9809105_amd import inputs
-    n = A64.shape[0]
+    m, k = A64.shape
+    n = B64.shape[1]
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     # calibrate on one row per core of each product, then size the sample
     # (a multiple of the core count) to about target_s
-    cal = min(n, cores)
-    rows = inputs.sample_rows(n, cal, seed=7)
+    # one output row of C or dA costs 2 N Kd (resp. 2 N M) flops, of dB 2 M N
+    cal = min(m, k, cores)
+    rows_m = inputs.sample_rows(m, cal, seed=7)
+    rows_k = inputs.sample_rows(k, cal, seed=7)
     t0 = time.perf_counter()
-    oracle.gemm_rows(A64, B64, rows)
-    oracle.grad_a_rows(G64, B64, rows)
-    oracle.grad_b_rows(A64, G64, rows)
+    oracle.gemm_rows(A64, B64, rows_m)
+    oracle.grad_a_rows(G64, B64, rows_m)
+    oracle.grad_b_rows(A64, G64, rows_k)
     t_cal = time.perf_counter() - t0
     nrows = int(cal * target_s / max(t_cal, 1e-6))
-    nrows = max(cal, min(n, (nrows // cores) * cores))
-    rows = inputs.sample_rows(n, nrows, seed=8)
+    nrows = max(cal, min(m, k, (nrows // cores) * cores))
+    rows_m = inputs.sample_rows(m, nrows, seed=8)
+    rows_k = inputs.sample_rows(k, nrows, seed=8)
     t0 = time.perf_counter()
-    oracle.gemm_rows(A64, B64, rows)
-    oracle.grad_a_rows(G64, B64, rows)
-    oracle.grad_b_rows(A64, G64, rows)
+    oracle.gemm_rows(A64, B64, rows_m)
+    oracle.grad_a_rows(G64, B64, rows_m)
+    oracle.grad_b_rows(A64, G64, rows_k)
     dt = time.perf_counter() - t0
-    flops = 3 * 2.0 * nrows * n * n
+    flops = 2.0 * nrows * (n * k + n * k + m * n)
     return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
-            "sample": "%d of %d rows of each of C, dA, dB (n=%d, FP64 triple loop, %.1f s)"
-                      % (nrows, n, n, dt)}
+            "sample": "%d sampled rows of each of C, dA, dB (M=%d Kd=%d N=%d, FP64 triple loop, %.1f s)"
+                      % (nrows, m, k, n, dt)}
 
 
 def main():
@@ -110,10 +119,15 @@ def main():
     import paper_cs_9809105_amd as hs
     from paper_cs_9809105_amd import inputs
 
-    n, p, K = args.n, args.p, args.K
-    A64 = inputs.row_scaled((n, n), seed=inputs.BASE_SEED + 2)
-    B64 = inputs.row_scaled((n, n), seed=inputs.BASE_SEED + 3)
-    G64 = inputs.normal((n, n), seed=inputs.BASE_SEED + 4)
+    p, K = args.p, args.K
+    if args.shape:
+        m, kd, n = (int(x) for x in args.shape.split(","))
+    else:
+        m = kd = n = args.n
+    gen = inputs.row_scaled if args.inputs == "rowscaled" else inputs.uniform
+    A64 = gen((m, kd), seed=inputs.BASE_SEED + 2)
+    B64 = gen((kd, n), seed=inputs.BASE_SEED + 3)
+    G64 = inputs.normal((m, n), seed=inputs.BASE_SEED + 4)
     A = torch.from_numpy(A64).float().cuda()
     B = torch.from_numpy(B64).float().cuda()
     G = torch.from_numpy(G64).float().cuda()
@@ -129,12 +143,13 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    useful = 3 * 2.0 * n ** 3
+    useful = 3 * 2.0 * m * kd * n
     wall, kern_ms, launches = run_form(hs, torch, A, B, G, args.form, p, K, args.steps, args.warmup)
     ms_step = wall * 1e3 / args.steps
     value = useful * args.steps / wall / 1e12
     avg_kernel_ms = kern_ms / max(launches, 1)
-    mfma_flops = MFMA_PRODUCTS[args.form] * 2.0 * n ** 3      # per main-kernel launch
+    mfma_flops = MFMA_PRODUCTS[args.form] * 2.0 * m * kd * n  # per main-kernel launch (all three
+    # products of a step have the same flop count)
     achieved = mfma_flops / (avg_kernel_ms * 1e-3) / 1e12
     peak = PEAK[MFMA_PEAK_KEY[args.form]]
 
@@ -149,14 +164,17 @@ def main():
     if args.cpu_seconds > 0:
         cpu = cpu_baseline(A64, B64, G64, args.cpu_seconds)
 
+    square = m == kd == n
+    shape_txt = "square n=%d" % n if square else "A %dx%d, B %dx%d" % (m, kd, kd, n)
+    in_txt = ("row-scaled N(0,1) A and B" if args.inputs == "rowscaled" else "U[-1,1] A and B")
     out = {
         "metric": "TFLOP/s at n=8192: split-BF16 (FP32-accurate) vs plain FP32 GEMM; fwd+bwd",
         "value": value, "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "bf16x3" if args.form == "split3_bf16" else args.form, "data": "synthetic",
-        "config": {"workload": "hyper-systolic C=A.B + dA=G.B^T + dB=A^T.G, square n=%d, "
-                               "row-scaled N(0,1) A and B, N(0,1) G" % n,
-                   "n": n, "p": p, "K": K, "form": args.form},
+        "config": {"workload": "hyper-systolic C=A.B + dA=G.B^T + dB=A^T.G, %s, %s, N(0,1) G"
+                               % (shape_txt, in_txt),
+                   "M": m, "Kd": kd, "N": n, "p": p, "K": K, "form": args.form},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": None,
                      "kernel": "mm_kernel (main MFMA loop)", "avg_kernel_ms": avg_kernel_ms,

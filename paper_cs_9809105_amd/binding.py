@@ -152,9 +152,9 @@ def _stream(stream):
 
 def _workspace(nbytes, device):
     torch = _torch()
-    if nbytes == SIZE_MAX:
-        raise HsError(HS_ERR_INVALID_VALUE, "hs_workspace_size")
-    if nbytes == 0:
+    if nbytes == SIZE_MAX or nbytes == 0:
+        # SIZE_MAX: the arguments are invalid; the entry point itself then
+        # rejects them (before any launch) with the precise status code
         return None, 0
     return torch.empty(nbytes, dtype=torch.uint8, device=device), nbytes
 

@@ -21,6 +21,7 @@ hipError_t launch_backshift(int f64, const void *W, int64_t plane, int K, int64_
                             void *Cout, int64_t ldc, hipStream_t st);
 hipError_t launch_fill_zero(int f64, void *Cout, int64_t M, int64_t N, int64_t ldc, hipStream_t st);
 hipError_t launch_gemv(int f64, const GemvArgs &a, hipStream_t st);
+hipError_t launch_fp8_exps(const Fp8ExpArgs &a, int64_t tiles, hipStream_t st);
 int mm_tile_rows(int fam);
 int mm_tile_cols(int fam);
 int mm_chunks_per_stage(int fam, int form);
@@ -47,6 +48,8 @@ bool form_info(hs_dtype dt, FormInfo *f) {
         case HS_BF16: *f = {FAM_BF16, 0, PK_B16, 2, 0, 2}; return true;
         case HS_F16: *f = {FAM_F16, 0, PK_B16, 2, 0, 2}; return true;
         case HS_SPLIT3_BF16: *f = {FAM_BF16, 1, PK_SPLIT3, 4, 0, 2}; return true;
+        case HS_FP8_E4M3: *f = {FAM_FP8, 0, PK_FP8, 4, 0, 1}; return true;
+        case HS_FP8_E4M3_R1: *f = {FAM_FP8, 1, PK_FP8, 4, 0, 1}; return true;
         default: return false;
     }
 }
@@ -66,6 +69,8 @@ struct Plan {
     int64_t M, N, Kd;
     OperandGeom ga, gb;
     size_t off_a, off_b, off_w, total;
+    size_t off_ea, off_eb;            // fp8: tile exponents of each operand
+    int64_t tiles_k, tiles_ra, tiles_rb;
 };
 
 // Threads of the pack kernel: one per 16-byte unit; a K-major source is
@@ -89,24 +94,32 @@ hs_status make_plan(int64_t M, int64_t N, int64_t Kd, hs_dtype dt, hs_schedule s
     const int CPS = mm_chunks_per_stage(P->f.fam, P->f.form);
     if (P->K > BMT) return HS_ERR_NOT_SUPPORTED;   // K groups of >= 1 row per tile
     const int p = P->p;
-    const int KC = 32 / P->f.packed_esz;
+    const bool fp8 = P->f.fam == FAM_FP8;
+    const int CBY = fp8 ? 64 : 32;                  // chunk bytes
+    const int KC = CBY / P->f.packed_esz;
     const int64_t S_r = std::max<int64_t>(1, ceil_div(M, p));
     const int64_t S_k = std::max<int64_t>(1, ceil_div(Kd, p));
     const int64_t nch = ceil_div(ceil_div(S_k, KC), CPS) * CPS;
     const int MS = (int)std::min<int64_t>(BMT / P->K, S_r);
-    const int NP = P->f.form == 1 ? 3 : 1;
+    const int NP = fp8 ? (P->f.form == 1 ? 2 : 1) : (P->f.form == 1 ? 3 : 1);
+    if (fp8) {
+        // every 32-row / 32-column MFMA tile and every 64-deep chunk must lie
+        // inside one 128 x 128 scale tile: whole 64-chunks per block, 32-row
+        // aligned stripes and groups
+        if (S_k % 64 != 0 || S_r % 32 != 0 || MS % 32 != 0) return HS_ERR_NOT_SUPPORTED;
+    }
 
     OperandGeom &a = P->ga;
     a.R = M; a.Kd = Kd; a.striped = 1; a.S_r = S_r; a.grp_rows = MS;
     a.GS = ceil_div(S_r, MS); a.n_groups = (int64_t)p * a.GS; a.p = p;
-    a.S_k = S_k; a.nch = nch; a.chunk_bytes = 32; a.pieces = NP;
-    a.piece_bytes = a.n_groups * p * nch * MS * 32;
+    a.S_k = S_k; a.nch = nch; a.chunk_bytes = CBY; a.pieces = NP;
+    a.piece_bytes = a.n_groups * p * nch * MS * CBY;
 
     OperandGeom &b = P->gb;
     b.R = N; b.Kd = Kd; b.striped = 0; b.S_r = 0; b.grp_rows = BNT;
     b.GS = ceil_div(N, BNT); b.n_groups = b.GS; b.p = p;
-    b.S_k = S_k; b.nch = nch; b.chunk_bytes = 32; b.pieces = NP;
-    b.piece_bytes = b.n_groups * p * nch * BNT * 32;
+    b.S_k = S_k; b.nch = nch; b.chunk_bytes = CBY; b.pieces = NP;
+    b.piece_bytes = b.n_groups * p * nch * BNT * CBY;
 
     const int64_t nwg = (int64_t)p * a.GS * b.GS;
     if (nwg > std::numeric_limits<int32_t>::max()) return HS_ERR_NOT_SUPPORTED;
@@ -122,6 +135,14 @@ hs_status make_plan(int64_t M, int64_t N, int64_t Kd, hs_dtype dt, hs_schedule s
     P->off_b = off; off = align_up(off + (size_t)(b.piece_bytes * NP));
     P->off_w = off;
     if (P->K > 1) off = align_up(off + (size_t)P->K * M * N * (P->f.out_f64 ? 8 : 4));
+    P->tiles_k = ceil_div(Kd, FP8_TILE);
+    P->tiles_ra = ceil_div(M, FP8_TILE);
+    P->tiles_rb = ceil_div(N, FP8_TILE);
+    P->off_ea = P->off_eb = off;
+    if (fp8) {
+        P->off_ea = off; off = align_up(off + (size_t)P->tiles_ra * P->tiles_k * 2 * sizeof(int32_t));
+        P->off_eb = off; off = align_up(off + (size_t)P->tiles_rb * P->tiles_k * 2 * sizeof(int32_t));
+    }
     P->total = (M == 0 || N == 0 || Kd == 0) ? 0 : off;
     return HS_OK;
 }
@@ -152,6 +173,9 @@ int pack_vec_ok(const Plan &P, const Operand &X) {
     if (P.f.pack == PK_SPLIT3) {                     // 8 fp32 per unit (two loads)
         return (X.ld % 4 == 0 && aligned(X.ptr, 16) && P.ga.S_k % 8 == 0 && P.Kd % 8 == 0) ? 1 : 0;
     }
+    if (P.f.pack == PK_FP8) {                        // 16 fp32 per unit (four loads)
+        return (X.ld % 4 == 0 && aligned(X.ptr, 16) && P.ga.S_k % 16 == 0 && P.Kd % 16 == 0) ? 1 : 0;
+    }
     return (X.ld * in % 16 == 0 && aligned(X.ptr, 16) && P.ga.S_k % ue == 0 && P.Kd % ue == 0) ? 1 : 0;
 }
 
@@ -163,17 +187,28 @@ hs_status run_product(const Plan &P, const Operand &X, const Operand &Y, void *o
     if (P.M == 0 || P.N == 0) return HS_OK;
     if (P.Kd == 0) return launch_status(launch_fill_zero(f64, out, P.M, P.N, ldo, stream));
     uint8_t *w = (uint8_t *)ws;
+    const bool fp8 = P.f.fam == FAM_FP8;
+    int32_t *ea = (int32_t *)(w + P.off_ea), *eb = (int32_t *)(w + P.off_eb);
+    if (fp8) {   // per-tile exponents of both operands (operand preparation)
+        Fp8ExpArgs xa{(const float *)X.ptr, X.ld, X.kmajor, P.M, P.Kd, P.tiles_k, P.f.form, ea};
+        Fp8ExpArgs xb{(const float *)Y.ptr, Y.ld, Y.kmajor, P.N, P.Kd, P.tiles_k, P.f.form, eb};
+        if (launch_fp8_exps(xa, P.tiles_ra * P.tiles_k, stream) != hipSuccess ||
+            launch_fp8_exps(xb, P.tiles_rb * P.tiles_k, stream) != hipSuccess)
+            return HS_ERR_LAUNCH_FAILED;
+    }
 
     PackArgs pa{};
     pa.src = X.ptr; pa.ld = X.ld; pa.g = P.ga; pa.dst = w + P.off_a;
     pa.total_units = pack_units(P.ga, X.kmajor);
     pa.vec = pack_vec_ok(P, X);
+    pa.exps = ea; pa.exp_tiles_k = P.tiles_k; pa.refine = P.f.form;
     hipError_t e = launch_pack(P.f.pack, X.kmajor, pa, stream);
     if (e != hipSuccess) return HS_ERR_LAUNCH_FAILED;
     PackArgs pb{};
     pb.src = Y.ptr; pb.ld = Y.ld; pb.g = P.gb; pb.dst = w + P.off_b;
     pb.total_units = pack_units(P.gb, Y.kmajor);
     pb.vec = pack_vec_ok(P, Y);
+    pb.exps = eb; pb.exp_tiles_k = P.tiles_k; pb.refine = P.f.form;
     e = launch_pack(P.f.pack, Y.kmajor, pb, stream);
     if (e != hipSuccess) return HS_ERR_LAUNCH_FAILED;
 
@@ -189,6 +224,8 @@ hs_status run_product(const Plan &P, const Operand &X, const Operand &Y, void *o
     m.p = P.p; m.K = P.K; m.Kt = P.Kt;
     m.MS = P.ga.grp_rows; m.GS = P.ga.GS; m.nch = P.ga.nch; m.S_r = P.ga.S_r;
     m.M = P.M; m.N = P.N; m.n_ntiles = P.gb.GS; m.out_f64 = f64;
+    m.a_exps = ea; m.b_exps = eb; m.a_tiles_k = P.tiles_k; m.b_tiles_k = P.tiles_k;
+    m.S_k = P.ga.S_k; m.Kd = P.Kd;
 
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (g_prof) {

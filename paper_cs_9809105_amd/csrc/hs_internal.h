@@ -28,7 +28,22 @@ enum PackKind : int {
     PK_F32 = 1,      // f32 -> f32
     PK_B16 = 2,      // 16-bit -> same 16-bit (bf16 or f16 copy)
     PK_SPLIT3 = 3,   // f32 -> three bf16 pieces
-    PK_FP8 = 4,      // f32 -> e4m3 q0 (+ q1) with per-tile scales
+    PK_FP8 = 4,      // f32 -> e4m3 q0 (+ q1) with per-tile power-of-two scales
+};
+
+// FP8 scale tiles: 128 x 128 blocks of the logical operand (rows x
+// contraction); per tile two int32 exponents {e, e1}: q0 = e4m3(a 2^e) and,
+// with refinement, q1 = e4m3((a 2^e - q0) 2^e1).
+const int FP8_TILE = 128;
+
+struct Fp8ExpArgs {
+    const float *src;
+    int64_t ld;
+    int kmajor;
+    int64_t R, Kd;
+    int64_t tiles_k;          // tiles along the contraction
+    int refine;
+    int32_t *exps;            // [tile_r][tile_k][2]
 };
 
 struct OperandGeom {
@@ -52,12 +67,11 @@ struct PackArgs {
     int64_t ld;
     OperandGeom g;
     void *dst;
-    uint8_t *scale_dst;   // fp8 only: [piece][group][kb][chunk][row][2]
-    int64_t scale_piece_bytes;
-    const float *tile_scale; // fp8 only: per 128x128 tile exponent info
-    int64_t tiles_r, tiles_k;
     int64_t total_units;     // < 2^31
     int vec;                 // K-major source: 16-byte vector loads are legal
+    const int32_t *exps;     // fp8 only: tile exponents (Fp8ExpArgs)
+    int64_t exp_tiles_k;
+    int refine;              // fp8 only: write q1 as the second piece
 };
 
 struct MainArgs {
@@ -66,10 +80,11 @@ struct MainArgs {
     const uint8_t *B;        // packed travelling operand
     int64_t b_piece;
     int64_t a_bytes, b_bytes; // total packed bytes (all pieces), each < 4 GiB
-    const uint8_t *a_scale;  // fp8 only
-    int64_t a_scale_piece;
-    const uint8_t *b_scale;
-    int64_t b_scale_piece;
+    const int32_t *a_exps;   // fp8 only: tile exponents of each operand
+    const int32_t *b_exps;
+    int64_t a_tiles_k, b_tiles_k;
+    int64_t S_k;             // contraction block length (fp8 scale lookup)
+    int64_t Kd;              // contraction length
     void *out;               // partial planes (K > 1) or the result (K == 1)
     int64_t ldo;             // row stride of out (elements)
     int64_t plane;           // elements between partial planes

@@ -34,6 +34,7 @@ typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));   // 16 bytes, a native vector
+typedef int i32x8 __attribute__((ext_vector_type(8)));             // 32 fp8 values
 
 // ---------------------------------------------------------------------------
 // number formats
@@ -47,14 +48,101 @@ DEVI uint16_t f32_to_bf16_rne(float x) {
 }
 DEVI float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
+// float -> e4m3 (OCP FP8: 1 sign, 4 exponent bits with bias 7, 3 mantissa
+// bits; largest finite 448, no infinities), round to nearest, ties to even,
+// saturating at 448.  Subnormals are m * 2^-9, m = 1..7; normals
+// (8 + m) * 2^(E-3) for E = -6..8.  Scaling by powers of two is exact, so
+// each step below is exact except the single rint().
+DEVI uint8_t f32_to_e4m3_rne(float x) {
+    const uint32_t sign = (__float_as_uint(x) >> 24) & 0x80u;
+    const float ax = fabsf(x);
+    uint32_t code;
+    if (ax < 0.015625f) {                                  // below 2^-6
+        code = (uint32_t)rintf(ax * 512.0f);               // 0..8 (8 is 2^-6, code 0x08)
+    } else {
+        int E = (int)((__float_as_uint(ax) >> 23) & 0xffu) - 127;   // floor(log2 ax)
+        uint32_t mq = (uint32_t)rintf(ldexpf(ax, 3 - E));  // 8..16
+        if (mq == 16u) { mq = 8u; ++E; }
+        code = E + 7 > 15 ? 0x7fu : (((uint32_t)(E + 7) << 3) | (mq - 8u));
+        if (code > 0x7eu) code = 0x7eu;                    // 0x7f is NaN: saturate to 448
+    }
+    return (uint8_t)(sign | code);
+}
+DEVI float e4m3_to_f32(uint32_t c) {
+    const int e = (int)((c >> 3) & 15u), m = (int)(c & 7u);
+    const float v = e == 0 ? ldexpf((float)m, -9) : ldexpf((float)(8 + m), e - 10);
+    return (c & 0x80u) ? -v : v;
+}
+
+// Largest e with amax * 2^e <= 448 (0 for an all-zero tile), clamped so that
+// the block-scale byte 127 - e stays a finite E8M0 value.
+DEVI int fp8_exponent(float amax) {
+    if (!(amax > 0.0f) || !(amax < 3.0e38f)) return 0;
+    int E;
+    const float m = frexpf(amax, &E);                      // amax = m 2^E, m in [0.5, 1)
+    int e = (m <= 0.875f ? 9 : 8) - E;                     // 448 = 0.875 * 2^9
+    return e < -126 ? -126 : (e > 126 ? 126 : e);
+}
+
 // ---------------------------------------------------------------------------
 // pack
 // ---------------------------------------------------------------------------
+// One workgroup per 128 x 128 scale tile: amax of the tile, then (with
+// refinement) amax of the residuals a 2^e - q0, both turned into exponents.
+__global__ __launch_bounds__(256) void fp8_tile_exp_kernel(Fp8ExpArgs a) {
+    __shared__ float red[256];
+    const int64_t tr = blockIdx.x / a.tiles_k, tc = blockIdx.x % a.tiles_k;
+    const int tid = threadIdx.x;
+    auto elem = [&](int idx, bool &ok) -> float {
+        // K-major sources are walked along the contraction, others along rows
+        const int64_t r = tr * FP8_TILE + (a.kmajor ? idx / FP8_TILE : idx % FP8_TILE);
+        const int64_t k = tc * FP8_TILE + (a.kmajor ? idx % FP8_TILE : idx / FP8_TILE);
+        ok = r < a.R && k < a.Kd;
+        return ok ? (a.kmajor ? a.src[r * a.ld + k] : a.src[k * a.ld + r]) : 0.0f;
+    };
+    float m = 0.0f;
+    for (int idx = tid; idx < FP8_TILE * FP8_TILE; idx += 256) {
+        bool ok;
+        m = fmaxf(m, fabsf(elem(idx, ok)));
+    }
+    red[tid] = m;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w) red[tid] = fmaxf(red[tid], red[tid + w]);
+        __syncthreads();
+    }
+    const int e = fp8_exponent(red[0]);
+    int e1 = 0;
+    if (a.refine) {
+        __syncthreads();
+        float mr = 0.0f;
+        for (int idx = tid; idx < FP8_TILE * FP8_TILE; idx += 256) {
+            bool ok;
+            const float xs = ldexpf(elem(idx, ok), e);
+            mr = fmaxf(mr, fabsf(xs - e4m3_to_f32(f32_to_e4m3_rne(xs))));
+        }
+        red[tid] = mr;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if (tid < w) red[tid] = fmaxf(red[tid], red[tid + w]);
+            __syncthreads();
+        }
+        e1 = red[0] > 0.0f ? fp8_exponent(red[0]) : 0;
+        if (e1 > 127 - e) e1 = 127 - e;                    // keep 127 - e - e1 >= 0
+        if (e1 < -127 - e) e1 = -127 - e;
+    }
+    if (tid == 0) {
+        a.exps[blockIdx.x * 2] = e;
+        a.exps[blockIdx.x * 2 + 1] = e1;
+    }
+}
+
 template <int KIND> struct PackTraits;
 template <> struct PackTraits<PK_F64> { typedef double S; static const int UE = 2; static const int ESZ = 8; static const int NP = 1; };
 template <> struct PackTraits<PK_F32> { typedef float S; static const int UE = 4; static const int ESZ = 4; static const int NP = 1; };
 template <> struct PackTraits<PK_B16> { typedef uint16_t S; static const int UE = 8; static const int ESZ = 2; static const int NP = 1; };
 template <> struct PackTraits<PK_SPLIT3> { typedef float S; static const int UE = 8; static const int ESZ = 2; static const int NP = 3; };
+template <> struct PackTraits<PK_FP8> { typedef float S; static const int UE = 16; static const int ESZ = 1; static const int NP = 2; };
 
 // One thread makes one 16-byte unit of the packed image (for the split form,
 // the same unit of each of the three pieces).  Consecutive threads take
@@ -160,6 +248,27 @@ __global__ __launch_bounds__(256) void pack_kernel(PackArgs a) {
         w[2] = vals_h[4] | ((uint32_t)vals_h[5] << 16);
         w[3] = vals_h[6] | ((uint32_t)vals_h[7] << 16);
         *(u32x4 *)dst = w;
+    } else if constexpr (KIND == PK_FP8) {
+        // all 16 elements of the unit lie in one 128 x 128 scale tile
+        int e = 0, e1 = 0;
+        if (rvalid && kk0 < g.Kd) {
+            const int64_t t2 = ((row / FP8_TILE) * a.exp_tiles_k + kk0 / FP8_TILE) * 2;
+            e = a.exps[t2];
+            e1 = a.exps[t2 + 1];
+        }
+        u32x4 w0 = {0, 0, 0, 0}, w1 = {0, 0, 0, 0};
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const float xs = ldexpf(vals_f[i], e);             // exact
+            const uint32_t q0 = f32_to_e4m3_rne(xs);
+            w0[i / 4] |= q0 << ((i % 4) * 8);
+            if (a.refine) {
+                const uint32_t q1 = f32_to_e4m3_rne(ldexpf(xs - e4m3_to_f32(q0), e1));
+                w1[i / 4] |= q1 << ((i % 4) * 8);
+            }
+        }
+        *(u32x4 *)dst = w0;
+        if (a.refine) *(u32x4 *)(dst + g.piece_bytes) = w1;
     } else {   // PK_SPLIT3: a0 = bf16(a), a1 = bf16(a - a0), a2 = bf16(a - a0 - a1)
         uint16_t p0[8], p1[8], p2[8];
 #pragma unroll
@@ -199,17 +308,23 @@ template <> struct Mfma<FAM_F64> { static const int T = 16; typedef f64x4 Acc; }
 template <> struct Mfma<FAM_F32> { static const int T = 32; typedef f32x16 Acc; };
 template <> struct Mfma<FAM_BF16> { static const int T = 32; typedef f32x16 Acc; };
 template <> struct Mfma<FAM_F16> { static const int T = 32; typedef f32x16 Acc; };
+template <> struct Mfma<FAM_FP8> { static const int T = 32; typedef f32x16 Acc; };
+
+// Pieces per operand: split-BF16 3, refined FP8 2 (q0, q1), otherwise 1.
+template <int FAM, int FORM>
+struct Pieces { static const int NP = FAM == FAM_FP8 ? (FORM ? 2 : 1) : Form<FORM>::NP; };
 
 template <int FAM, int FORM, int BM, int BN, int CPS, int WAVES>
 struct MmCfg {
-    static const int NP = Form<FORM>::NP;
+    static const int NP = Pieces<FAM, FORM>::NP;
     static const int NT = 64 * WAVES;                   // threads per workgroup
-    static const int CB = 32;                           // bytes per chunk row
+    static const int CB = FAM == FAM_FP8 ? 64 : 32;     // bytes per chunk row
+    static const int NPL = CB / 16;                     // 16-byte planes per chunk row
     static const int A_STAGE = NP * CPS * BM * CB;      // LDS bytes per stage
     static const int B_STAGE = NP * CPS * BN * CB;
-    static const int UA = NP * CPS * BM * 2 / NT;       // 16-byte loads per thread
-    static const int UB = NP * CPS * BN * 2 / NT;
-    static_assert(UA * NT == NP * CPS * BM * 2 && UB * NT == NP * CPS * BN * 2, "tile/threads");
+    static const int UA = NP * CPS * BM * NPL / NT;     // 16-byte loads per thread
+    static const int UB = NP * CPS * BN * NPL / NT;
+    static_assert(UA * NT == NP * CPS * BM * NPL && UB * NT == NP * CPS * BN * NPL, "tile/threads");
     static const int WM = BM / 2, WN = BN / (WAVES / 2); // waves: 2 along rows, WAVES/2 along columns
     static const int MT = Mfma<FAM>::T;
     static const int TM = WM / MT, TN = WN / MT;
@@ -219,12 +334,50 @@ struct MmCfg {
 
 // One pipeline stage of block products from LDS: for every chunk of the
 // stage, the wave's MFMA tiles accumulate A_rows x B_cols.
-template <int FAM, int FORM, int BM, int BN, int CPS, int WAVES, typename AccArr>
-DEVI void mm_compute(AccArr &acc, const uint8_t *Ab, const uint8_t *Bb, int lane, int wm, int wn) {
+// For FP8, sa[c][P][mi] / sb[c][P][ni] are the E8M0 block-scale bytes of
+// chunk c, piece P, row / column tile (uniform across the wave).
+template <int FAM, int FORM, int BM, int BN, int CPS, int WAVES, typename AccArr, typename SA, typename SB>
+DEVI void mm_compute(AccArr &acc, const uint8_t *Ab, const uint8_t *Bb, int lane, int wm, int wn,
+                     const SA &sa, const SB &sb) {
     typedef MmCfg<FAM, FORM, BM, BN, CPS, WAVES> C;
 #pragma unroll
     for (int c = 0; c < CPS; ++c) {
-        if constexpr (FAM == FAM_F64) {
+        if constexpr (FAM == FAM_FP8) {
+            // lane group g holds contraction elements 32g..32g+31 of the
+            // 64-element chunk: planes 2g and 2g+1 of the row
+            const int r32 = lane & 31, g = lane >> 5;
+            i32x8 bv[C::NP][C::TN];
+#pragma unroll
+            for (int P = 0; P < C::NP; ++P)
+#pragma unroll
+                for (int ni = 0; ni < C::TN; ++ni) {
+                    const uint8_t *q = Bb + (P * CPS + c) * BN * C::CB + (2 * g) * BN * 16 + (wn * C::WN + ni * 32 + r32) * 16;
+                    const u32x4 lo = *(const u32x4 *)q, hi = *(const u32x4 *)(q + BN * 16);
+                    bv[P][ni] = i32x8{(int)lo[0], (int)lo[1], (int)lo[2], (int)lo[3], (int)hi[0], (int)hi[1], (int)hi[2], (int)hi[3]};
+                }
+#pragma unroll
+            for (int mi = 0; mi < C::TM; ++mi) {
+                i32x8 av[C::NP];
+#pragma unroll
+                for (int P = 0; P < C::NP; ++P) {
+                    const uint8_t *q = Ab + (P * CPS + c) * BM * C::CB + (2 * g) * BM * 16 + (wm * C::WM + mi * 32 + r32) * 16;
+                    const u32x4 lo = *(const u32x4 *)q, hi = *(const u32x4 *)(q + BM * 16);
+                    av[P] = i32x8{(int)lo[0], (int)lo[1], (int)lo[2], (int)lo[3], (int)hi[0], (int)hi[1], (int)hi[2], (int)hi[3]};
+                }
+#pragma unroll
+                for (int ni = 0; ni < C::TN; ++ni) {
+                    if constexpr (C::NP == 2) {
+                        // q1 q0', q0 q1', q0 q0': smallest first
+                        acc[mi][ni] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                            av[1], bv[0][ni], acc[mi][ni], 0, 0, 0, sa[c][1][mi], 0, sb[c][0][ni]);
+                        acc[mi][ni] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                            av[0], bv[1][ni], acc[mi][ni], 0, 0, 0, sa[c][0][mi], 0, sb[c][1][ni]);
+                    }
+                    acc[mi][ni] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                        av[0], bv[0][ni], acc[mi][ni], 0, 0, 0, sa[c][0][mi], 0, sb[c][0][ni]);
+                }
+            }
+        } else if constexpr (FAM == FAM_F64) {
             const int r16 = lane & 15, g = lane >> 4;
             double av[C::TM], bv[C::TN];
 #pragma unroll
@@ -351,22 +504,22 @@ void mm_kernel(MainArgs a) {
 #pragma unroll
     for (int q = 0; q < C::UA; ++q) {
         const int ui = tid + C::NT * q;              // unit: [slab][plane][row]
-        const int slab = ui / (BM * 2);
-        const int within = ui % (BM * 2);
-        const int half = within / BM, rho = within % BM;
+        const int slab = ui / (BM * C::NPL);
+        const int within = ui % (BM * C::NPL);
+        const int plane = within / BM, rho = within % BM;
         const int P = slab / CPS, c = slab % CPS;
         const int l = rho / MS, i = rho % MS;
         const int64_t grp = (int64_t)((v - l + p) % p) * a.GS + msub;
         a_off[q] = l < K ? (uint32_t)((int64_t)P * a.a_piece + grp * (int64_t)p * nch * MS * C::CB +
-                                      (int64_t)c * MS * C::CB + (int64_t)(half * MS + i) * 16)
+                                      (int64_t)c * MS * C::CB + (int64_t)(plane * MS + i) * 16)
                          : 0u;
     }
     uint32_t b_off[C::UB];
 #pragma unroll
     for (int q = 0; q < C::UB; ++q) {
         const int ui = tid + C::NT * q;
-        const int slab = ui / (BN * 2);
-        const int within = ui % (BN * 2);
+        const int slab = ui / (BN * C::NPL);
+        const int within = ui % (BN * C::NPL);
         const int P = slab / CPS, c = slab % CPS;
         b_off[q] = (uint32_t)((int64_t)P * a.b_piece + ntile * (int64_t)p * nch * BN * C::CB +
                               (int64_t)c * BN * C::CB + (int64_t)within * 16);
@@ -388,6 +541,62 @@ void mm_kernel(MainArgs a) {
             cs = 0;
             kb += K;
             if (kb >= p) kb -= p;
+        }
+    };
+
+    // FP8: block-scale bytes of the stage being multiplied.  Every 32-row
+    // (32-column) MFMA tile and every 64-deep chunk lies inside one 128 x 128
+    // scale tile (the host checks the alignment), so each scale is uniform
+    // across the wave: 127 - e for q0, 127 - e - e1 for q1.
+    int sa[CPS][C::NP][C::TM], sb[CPS][C::NP][C::TN];
+    int kbc = v, csc = 0;                               // stage being multiplied
+    int tra[C::TM], trb[C::TN];
+    if constexpr (FAM == FAM_FP8) {
+#pragma unroll
+        for (int mi = 0; mi < C::TM; ++mi) {
+            const int rho0 = wm * C::WM + mi * 32;
+            const int l = rho0 / MS, i0 = rho0 % MS;
+            int64_t row0 = (int64_t)((v - l + p) % p) * a.S_r + msub * MS + i0;
+            row0 = row0 < a.M ? row0 : a.M - 1;
+            tra[mi] = (int)(row0 / FP8_TILE);
+        }
+#pragma unroll
+        for (int ni = 0; ni < C::TN; ++ni) {
+            int64_t col0 = ntile * BN + wn * C::WN + ni * 32;
+            col0 = col0 < a.N ? col0 : a.N - 1;
+            trb[ni] = (int)(col0 / FP8_TILE);
+        }
+    }
+    auto stage_scales = [&]() {
+        if constexpr (FAM == FAM_FP8) {
+            typedef const __attribute__((address_space(4))) int32_t cint;
+            cint *ea = (cint *)a.a_exps;
+            cint *eb = (cint *)a.b_exps;
+#pragma unroll
+            for (int c = 0; c < CPS; ++c) {
+                int64_t kk = (int64_t)kbc * a.S_k + (int64_t)(csc * CPS + c) * 64;
+                kk = kk < a.Kd ? kk : a.Kd - 1;         // padding chunks hold zeros
+                const int tc = __builtin_amdgcn_readfirstlane((int)(kk / FP8_TILE));
+#pragma unroll
+                for (int mi = 0; mi < C::TM; ++mi) {
+                    const int t = __builtin_amdgcn_readfirstlane((int)((tra[mi] * a.a_tiles_k + tc) * 2));
+                    const int e = ea[t], e1 = ea[t + 1];
+                    sa[c][0][mi] = 127 - e;
+                    if constexpr (C::NP == 2) sa[c][1][mi] = 127 - e - e1;
+                }
+#pragma unroll
+                for (int ni = 0; ni < C::TN; ++ni) {
+                    const int t = __builtin_amdgcn_readfirstlane((int)((trb[ni] * a.b_tiles_k + tc) * 2));
+                    const int e = eb[t], e1 = eb[t + 1];
+                    sb[c][0][ni] = 127 - e;
+                    if constexpr (C::NP == 2) sb[c][1][ni] = 127 - e - e1;
+                }
+            }
+            if (++csc == spb) {
+                csc = 0;
+                kbc += K;
+                if (kbc >= p) kbc -= p;
+            }
         }
     };
 
@@ -423,9 +632,11 @@ void mm_kernel(MainArgs a) {
         fetch_offsets(ach, bch);                                                               \
         stage_load<C::UA, C::UB>(RLOAD, rsA, rsB, a_off, b_off, ach, bch);                     \
         stage_store<C::UA, C::UB, C::A_STAGE, C::NT>(RSTORE, ring + (slot ^ 1) * C::STAGE, tid); \
+        stage_scales();                                                                        \
         __builtin_amdgcn_sched_barrier(0);                                                     \
         mm_compute<FAM, FORM, BM, BN, CPS, WAVES>(acc, ring + slot * C::STAGE,                 \
-                                           ring + slot * C::STAGE + C::A_STAGE, lane, wm, wn); \
+                                           ring + slot * C::STAGE + C::A_STAGE, lane, wm, wn,  \
+                                           sa, sb);                                            \
         __syncthreads();                                                                       \
         if (++s >= nstages) break;                                                             \
     }
@@ -435,9 +646,11 @@ void mm_kernel(MainArgs a) {
         const int slot = (int)(s & 1);                                                         \
         fetch_offsets(ach, bch);                                                               \
         stage_load<C::UA, C::UB>(RLOAD, rsA, rsB, a_off, b_off, ach, bch);                     \
+        stage_scales();                                                                        \
         __builtin_amdgcn_sched_barrier(0);                                                     \
         mm_compute<FAM, FORM, BM, BN, CPS, WAVES>(acc, ring + slot * C::STAGE,                 \
-                                           ring + slot * C::STAGE + C::A_STAGE, lane, wm, wn); \
+                                           ring + slot * C::STAGE + C::A_STAGE, lane, wm, wn,  \
+                                           sa, sb);                                            \
         __builtin_amdgcn_sched_barrier(0);                                                     \
         stage_store<C::UA, C::UB, C::A_STAGE, C::NT>(RSTORE, ring + (slot ^ 1) * C::STAGE, tid); \
         __syncthreads();                                                                       \
@@ -597,6 +810,8 @@ hipError_t launch_pack(int kind, int kmajor, const PackArgs &a, hipStream_t st) 
         case PK_B16 * 2 + 1: HS_PACK(PK_B16, 1); break;
         case PK_SPLIT3 * 2: HS_PACK(PK_SPLIT3, 0); break;
         case PK_SPLIT3 * 2 + 1: HS_PACK(PK_SPLIT3, 1); break;
+        case PK_FP8 * 2: HS_PACK(PK_FP8, 0); break;
+        case PK_FP8 * 2 + 1: HS_PACK(PK_FP8, 1); break;
         default: return hipErrorInvalidValue;
     }
 #undef HS_PACK
@@ -624,6 +839,7 @@ int mm_tile_rows(int fam) { return fam == FAM_F64 ? 64 : 256; }
 int mm_tile_cols(int fam) { return fam == FAM_F64 ? 64 : 256; }
 int mm_chunks_per_stage(int fam, int form) {
     if (fam == FAM_F64) return 4;
+    if (fam == FAM_FP8) return form == 1 ? 1 : 2;
     if (fam == FAM_F32) return 2;
     return form == 1 ? 1 : 2;
 }
@@ -643,7 +859,15 @@ hipError_t launch_mm(int fam, int form, const MainArgs &a, hipStream_t st) {
     if (fam == FAM_F16) return launch_mm_t<FAM_F16, 0, 256, 256, 2, HS_WAVES_B16>(a, st);
     if (fam == FAM_BF16 && form == 0) return launch_mm_t<FAM_BF16, 0, 256, 256, 2, HS_WAVES_B16>(a, st);
     if (fam == FAM_BF16 && form == 1) return launch_mm_t<FAM_BF16, 1, 256, 256, 1, HS_WAVES_SPLIT>(a, st);
+    if (fam == FAM_FP8 && form == 0) return launch_mm_t<FAM_FP8, 0, 256, 256, 2, 8>(a, st);
+    if (fam == FAM_FP8 && form == 1) return launch_mm_t<FAM_FP8, 1, 256, 256, 1, 8>(a, st);
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_fp8_exps(const Fp8ExpArgs &a, int64_t tiles, hipStream_t st) {
+    if (tiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(fp8_tile_exp_kernel, dim3((unsigned)tiles), dim3(256), 0, st, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_backshift(int f64, const void *W, int64_t plane, int K, int64_t M, int64_t N,

@@ -114,6 +114,15 @@ def test_schedule_table_small_buffer():
     assert st == B.HS_ERR_INVALID_VALUE
 
 
+def test_fp8_workspace_sizes():
+    ws = B.hs_workspace_size
+    s1 = ws(B.HS_OP_GEMM, 1024, 1024, 1024, "fp8_e4m3", 8, 2)
+    s2 = ws(B.HS_OP_GEMM, 1024, 1024, 1024, "fp8_e4m3_r1", 8, 2)
+    assert s1 != B.SIZE_MAX and s2 > s1            # q1 pieces
+    assert ws(B.HS_OP_GEMM, 64, 64, 96, "fp8_e4m3", 2) == B.SIZE_MAX
+    assert ws(B.HS_OP_BACKWARD, 16384, 16384, 8192, "fp8_e4m3_r1", 64) != B.SIZE_MAX
+
+
 def test_workspace_sizes():
     ws = B.hs_workspace_size
     assert ws(B.HS_OP_GEMM, 0, 10, 10, "f32", 2) == 0
@@ -162,6 +171,10 @@ def _gemm(**kw):
     (dict(wsb=16), B.HS_ERR_WORKSPACE_TOO_SMALL),
     (dict(ws=FAKE + 64), B.HS_ERR_INVALID_VALUE),
     (dict(p=512, K=512), B.HS_ERR_NOT_SUPPORTED),
+    # FP8: contraction blocks must be whole 64-element chunks, stripes 32-row aligned
+    (dict(dt=B.HS_FP8_E4M3, m=64, n=64, k=96, lda=96, ldb=64, ldc=64, p=2), B.HS_ERR_NOT_SUPPORTED),
+    (dict(dt=B.HS_FP8_E4M3_R1, m=48, n=64, k=128, lda=128, ldb=64, ldc=64, p=2), B.HS_ERR_NOT_SUPPORTED),
+    (dict(dt=B.HS_FP8_E4M3_R1, m=256, n=64, k=768, lda=768, ldb=64, ldc=64, p=4, K=3), B.HS_ERR_INVALID_VALUE),
 ])
 def test_gemm_rejects(kw, code):
     assert _gemm(**kw) == code

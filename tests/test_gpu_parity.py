@@ -23,7 +23,11 @@ if gpu_available():
     import paper_cs_9809105_amd as hs
     from paper_cs_9809105_amd import autograd as hs_autograd
 
-TOL = {"f64": 1e-12, "f32": 1e-5, "split3_bf16": 1e-5, "bf16": 1.5e-2, "f16": 3e-3}
+TOL = {"f64": 1e-12, "f32": 1e-5, "split3_bf16": 1e-5, "bf16": 1.5e-2, "f16": 3e-3,
+       "fp8_e4m3": 1e-1, "fp8_e4m3_r1": 1e-2}
+# FP8 forms quantise inside the library; the refined form is also held to an
+# element bound relative to sum |a||b| (err_elem).
+FP8_R1_ELEM = 2.0 ** -10
 OUT = {"f64": "float64"}
 
 
@@ -295,3 +299,74 @@ def test_many_virtual_processors():
     for (m, n, k, p, K) in [(512, 384, 512, 256, 16), (4096, 64, 4096, 4096, 64)]:
         got, ref = _gemm_case("f32", m, n, k, p, K, False, seed=101)
         assert err_row(got, ref) <= 1e-5, (m, n, k, p, K)
+
+
+# ---------------------------------------------------------------------------
+# FP8 e4m3 with 128 x 128 power-of-two tile scales (plain and refined)
+# ---------------------------------------------------------------------------
+FP8 = ["fp8_e4m3", "fp8_e4m3_r1"]
+# shapes with contraction blocks of whole 64-chunks and 32-row stripes
+FP8_CASES = [(256, 256, 512, 4, 2), (512, 200, 1024, 8, 2), (320, 96, 640, 10, 1), (1024, 768, 2048, 16, 4),
+             (256, 300, 4096, 8, 8)]
+
+
+@pytest.mark.parametrize("dt", FP8)
+@pytest.mark.parametrize("case", FP8_CASES)
+@pytest.mark.parametrize("tn", [False, True])
+def test_fp8_forms(dt, case, tn):
+    from oracle.metrics import err_elem
+    m, n, k, p, K = case
+    got, ref = _gemm_case(dt, m, n, k, p, K, tn, seed=2000 + m + k)
+    assert not np.isnan(got).any()
+    e = err_row(got, ref)
+    assert e <= TOL[dt], (dt, case, tn, e)
+    if dt == "fp8_e4m3_r1":
+        A = inputs.uniform((k, m) if tn else (m, k), seed=2000 + m + k)
+        B = inputs.uniform((k, n), seed=2001 + m + k)
+        Af = A.astype(np.float32).astype(np.float64)
+        Bf = B.astype(np.float32).astype(np.float64)
+        absprod = oracle.gemm_tn(np.abs(Af), np.abs(Bf)) if tn else oracle.gemm(np.abs(Af), np.abs(Bf))
+        assert err_elem(got, ref, absprod) <= FP8_R1_ELEM
+
+
+@pytest.mark.parametrize("dt", FP8)
+@pytest.mark.parametrize("case", [(256, 256, 512, 4, 2), (512, 200, 1024, 8, 1)])
+def test_fp8_small_int_bit_exact(dt, case):
+    """Integers |x| <= 8 are exact in e4m3 under a power-of-two tile scale."""
+    m, n, k, p, K = case
+    got, ref = _gemm_case(dt, m, n, k, p, K, False, seed=78, gen=inputs.small_int)
+    assert np.array_equal(got, ref)
+
+
+def test_fp8_unsupported_alignment():
+    _skip_no_gpu()
+    A, _ = to_dev(inputs.uniform((100, 96), seed=1), "fp8_e4m3")
+    B, _ = to_dev(inputs.uniform((96, 64), seed=2), "fp8_e4m3")
+    with pytest.raises(hs.HsError) as e:
+        hs.hs_gemm(A, B, dtype="fp8_e4m3", p=2)       # blocks of 48: not whole 64-chunks
+    assert e.value.status == 2
+
+
+def test_fp8_r1_config_16384():
+    """A 16384 x 8192, B 8192 x 16384, U[-1, 1], FP8 refined, forward and
+    backward; error on 256 seeded sampled rows of C, dA and dB."""
+    _skip_no_gpu()
+    from oracle.metrics import err_elem
+    m, k, n = 16384, 8192, 16384
+    A, A64 = to_dev(inputs.uniform((m, k), seed=inputs.BASE_SEED + 4), "fp8_e4m3_r1")
+    B, B64 = to_dev(inputs.uniform((k, n), seed=inputs.BASE_SEED + 5), "fp8_e4m3_r1")
+    G, G64 = to_dev(inputs.normal((m, n), seed=inputs.BASE_SEED + 6), "fp8_e4m3_r1")
+    note("fp8 r1 16384")
+    C = hs.hs_gemm(A, B, dtype="fp8_e4m3_r1", p=64)
+    dA, dB = hs.hs_gemm_backward(A, B, G, dtype="fp8_e4m3_r1", p=64)
+    torch.cuda.synchronize()
+    rm = inputs.sample_rows(m, 256, seed=46)
+    rk = inputs.sample_rows(k, 256, seed=47)
+    refC = oracle.gemm_rows(A64, B64, rm)
+    eC = err_row(host(C)[rm], refC)
+    absC = oracle.gemm_rows(np.abs(A64), np.abs(B64), rm)
+    eCe = err_elem(host(C)[rm], refC, absC)
+    eA = err_row(host(dA)[rm], oracle.grad_a_rows(G64, B64, rm))
+    eB = err_row(host(dB)[rk], oracle.grad_b_rows(A64, G64, rk))
+    print("fp8 r1 16384: err_row C %.3e dA %.3e dB %.3e err_elem C %.3e" % (eC, eA, eB, eCe))
+    assert max(eC, eA, eB) <= 1e-2 and eCe <= FP8_R1_ELEM
