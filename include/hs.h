@@ -19,7 +19,11 @@
  * A and keeps columns; here rows are kept and B moves).  The "cshift" of a
  * stripe is the order in which its tiles are fetched from HBM into a
  * double-buffered LDS ring; the K auxiliary arrays C^l are K partial
- * accumulators; the back-shift is a fixed-order reduction.
+ * accumulators; the back-shift is a fixed-order reduction.  Each virtual
+ * processor enters its cycle of K~ steps (stride K) at block v mod K rather
+ * than at block v, so that all processors of a residue class hold the same
+ * travelling block at the same time and share it in cache; every processor
+ * still forms exactly the block products listed above.
  *
  * Conventions for every entry point
  *  - All matrices are dense and row-major; a leading dimension (ld*) is the

@@ -121,7 +121,8 @@ hs_status make_plan(int64_t M, int64_t N, int64_t Kd, hs_dtype dt, hs_schedule s
     b.S_k = S_k; b.nch = nch; b.chunk_bytes = CBY; b.pieces = NP;
     b.piece_bytes = b.n_groups * p * nch * BNT * CBY;
 
-    const int64_t nwg = (int64_t)p * a.GS * b.GS;
+    // grid (with padding to whole workgroup groups) must fit in 32 bits
+    const int64_t nwg = (int64_t)p * a.GS * b.GS * 2 + 64;
     if (nwg > std::numeric_limits<int32_t>::max()) return HS_ERR_NOT_SUPPORTED;
     // the main kernel addresses each packed operand with 32-bit offsets
     const int64_t kMaxPacked = (int64_t)0xFFFFFFF0;
@@ -224,6 +225,16 @@ hs_status run_product(const Plan &P, const Operand &X, const Operand &Y, void *o
     m.p = P.p; m.K = P.K; m.Kt = P.Kt;
     m.MS = P.ga.grp_rows; m.GS = P.ga.GS; m.nch = P.ga.nch; m.S_r = P.ga.S_r;
     m.M = P.M; m.N = P.N; m.n_ntiles = P.gb.GS; m.out_f64 = f64;
+    {   // 32 workgroups per XCD: grp_v class members x grp_t column tiles
+        int64_t gt = 1;
+        while (gt * 2 <= 8 && gt * 2 <= P.gb.GS) gt *= 2;
+        const int64_t members = (int64_t)P.Kt * P.ga.GS;
+        int64_t gv = 32 / gt;
+        while (gv > 1 && gv / 2 >= members) gv /= 2;
+        m.grp_t = gt; m.grp_v = gv;
+        m.n_tg = ceil_div(P.gb.GS, gt);
+        m.n_ug = ceil_div(members, gv);
+    }
     m.a_exps = ea; m.b_exps = eb; m.a_tiles_k = P.tiles_k; m.b_tiles_k = P.tiles_k;
     m.S_k = P.ga.S_k; m.Kd = P.Kd;
 

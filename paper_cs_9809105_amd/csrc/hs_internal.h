@@ -96,6 +96,8 @@ struct MainArgs {
     int64_t M, N;
     int64_t n_ntiles;
     int out_f64;             // out element type: 1 double, 0 float
+    // workgroup groups: grp_v class members x grp_t column tiles run together
+    int64_t grp_v, grp_t, n_ug, n_tg;
 };
 
 struct GemvArgs {

@@ -336,9 +336,14 @@ struct MmCfg {
 // stage, the wave's MFMA tiles accumulate A_rows x B_cols.
 // For FP8, sa[c][P][mi] / sb[c][P][ni] are the E8M0 block-scale bytes of
 // chunk c, piece P, row / column tile (uniform across the wave).
-template <int FAM, int FORM, int BM, int BN, int CPS, int WAVES, typename AccArr, typename SA, typename SB>
+//
+// `mid` runs once, right after the MFMAs of the first row tile of the first
+// chunk are issued: the pipeline puts the LDS writes of the next stage there,
+// so they overlap MFMAs instead of delaying this stage's first LDS reads.
+template <int FAM, int FORM, int BM, int BN, int CPS, int WAVES, typename AccArr, typename SA, typename SB,
+          typename Mid>
 DEVI void mm_compute(AccArr &acc, const uint8_t *Ab, const uint8_t *Bb, int lane, int wm, int wn,
-                     const SA &sa, const SB &sb) {
+                     const SA &sa, const SB &sb, Mid &&mid) {
     typedef MmCfg<FAM, FORM, BM, BN, CPS, WAVES> C;
 #pragma unroll
     for (int c = 0; c < CPS; ++c) {
@@ -376,6 +381,7 @@ DEVI void mm_compute(AccArr &acc, const uint8_t *Ab, const uint8_t *Bb, int lane
                     acc[mi][ni] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
                         av[0], bv[0][ni], acc[mi][ni], 0, 0, 0, sa[c][0][mi], 0, sb[c][0][ni]);
                 }
+                if (c == 0 && mi == 0) mid();
             }
         } else if constexpr (FAM == FAM_F64) {
             const int r16 = lane & 15, g = lane >> 4;
@@ -391,6 +397,7 @@ DEVI void mm_compute(AccArr &acc, const uint8_t *Ab, const uint8_t *Bb, int lane
 #pragma unroll
                 for (int ni = 0; ni < C::TN; ++ni)
                     acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[mi], bv[ni], acc[mi][ni], 0, 0, 0);
+            if (c == 0) mid();
         } else {
             const int r32 = lane & 31, g = lane >> 5;
             // all B fragments of the chunk, then one row tile of A at a time
@@ -434,6 +441,7 @@ DEVI void mm_compute(AccArr &acc, const uint8_t *Ab, const uint8_t *Bb, int lane
                         }
                     }
                 }
+                if (c == 0 && mi == 0) mid();
             }
         }
     }
@@ -483,12 +491,42 @@ void mm_kernel(MainArgs a) {
     const int wave = tid >> 6;
     const int wm = wave & 1, wn = wave >> 1;
 
-    // workgroup -> (virtual processor v, stripe sub-group msub, column tile)
+    // workgroup -> (virtual processor v, stripe sub-group msub, column tile).
+    // Workgroups are dealt to the 8 XCDs round robin; renumber them so each
+    // XCD runs a contiguous range.  Inside it, 32 consecutive workgroups (one
+    // per CU of the XCD) take G_V virtual processors of one residue class
+    // c = v mod K times G_T column tiles.  All members of a class hold the
+    // same travelling block at the same time (see the step order below), so
+    // the XCD's L2 serves each travelling tile to G_V workgroups and each
+    // static tile to G_T of them.
     int64_t bid = blockIdx.x;
-    const int64_t ntile = bid % a.n_ntiles;
-    bid /= a.n_ntiles;
-    const int64_t msub = bid % a.GS;
-    const int v = (int)(bid / a.GS);
+    {
+        const int64_t nwg = gridDim.x, xcd = bid % 8, per = nwg / 8, rem = nwg % 8;
+        bid = xcd * per + (xcd < rem ? xcd : rem) + bid / 8;
+    }
+#ifndef HS_CLASS_ORDER
+#define HS_CLASS_ORDER 1
+#endif
+    int64_t ntile, msub;
+    int v;
+    if (HS_CLASS_ORDER) {
+        const int64_t t_lo = bid % a.grp_t;  bid /= a.grp_t;
+        const int64_t u_lo = bid % a.grp_v;  bid /= a.grp_v;
+        const int64_t tg = bid % a.n_tg;     bid /= a.n_tg;
+        const int64_t ug = bid % a.n_ug;
+        const int c_class = (int)(bid / a.n_ug);
+        ntile = tg * a.grp_t + t_lo;
+        const int64_t u = ug * a.grp_v + u_lo;        // member of the class: (m, msub)
+        if (ntile >= a.n_ntiles || u >= (int64_t)a.Kt * a.GS) return;   // grid padding
+        msub = u % a.GS;
+        v = c_class + (int)(u / a.GS) * a.K;
+    } else {
+        if (bid >= (int64_t)a.p * a.GS * a.n_ntiles) return;            // grid padding
+        ntile = bid % a.n_ntiles;
+        bid /= a.n_ntiles;
+        msub = bid % a.GS;
+        v = (int)(bid / a.GS);
+    }
 
     const int p = a.p, K = a.K, MS = a.MS;
     const int64_t nch = a.nch;
@@ -527,11 +565,14 @@ void mm_kernel(MainArgs a) {
     const __amdgpu_buffer_rsrc_t rsA = packed_rsrc(a.A, (uint32_t)a.a_bytes);
     const __amdgpu_buffer_rsrc_t rsB = packed_rsrc(a.B, (uint32_t)a.b_bytes);
 
-    // Position of the next stage to fetch: step j holds travelling block
-    // kb = (v + jK) mod p (base A = (0, K, .., K)); cs counts the stages
-    // inside that block.  Past the last stage the position stays put, so the
-    // surplus fetches re-read the last stage (never used).
-    int kb = v, cs = 0, fetched = 0;
+    // Position of the next stage to fetch.  The steps of virtual processor
+    // v visit the travelling blocks kb = (v + jK) mod p, j = 0..K~-1 (base
+    // A = (0, K, .., K)), as a cycle of stride K; the cycle is entered at
+    // kb = v mod K, i.e. at step j = -(v div K) mod K~, so that every member
+    // of a residue class holds the same block at the same time.  cs counts
+    // the stages inside a block.  Past the last stage the position stays put,
+    // so the surplus fetches re-read the last stage (never used).
+    int kb = HS_CLASS_ORDER ? v % a.K : v, cs = 0, fetched = 0;
     const uint32_t a_stage = (uint32_t)(MS * C::CB), b_stage = (uint32_t)(BN * C::CB);
     auto fetch_offsets = [&](uint32_t &ach, uint32_t &bch) {
         const uint32_t ch = (uint32_t)kb * (uint32_t)nch + (uint32_t)(cs * CPS);
@@ -549,7 +590,7 @@ void mm_kernel(MainArgs a) {
     // scale tile (the host checks the alignment), so each scale is uniform
     // across the wave: 127 - e for q0, 127 - e - e1 for q1.
     int sa[CPS][C::NP][C::TM], sb[CPS][C::NP][C::TN];
-    int kbc = v, csc = 0;                               // stage being multiplied
+    int kbc = HS_CLASS_ORDER ? v % a.K : v, csc = 0;    // stage being multiplied
     int tra[C::TM], trb[C::TN];
     if constexpr (FAM == FAM_FP8) {
 #pragma unroll
@@ -622,10 +663,28 @@ void mm_kernel(MainArgs a) {
 #ifndef HS_STORE_FIRST
 #define HS_STORE_FIRST 1
 #endif
-#if HS_STORE_FIRST
-    // The LDS image of stage s + 1 is written at the top of stage s (its
-    // loads were issued a stage earlier), so the writes overlap the MFMAs
-    // of stage s and the barrier only closes the stage.
+#if HS_STORE_FIRST == 2
+    // The LDS image of stage s + 1 (loaded a stage earlier) is written during
+    // stage s, after the first row tile's MFMAs are issued, so the writes
+    // overlap MFMAs; the barrier closes the stage.
+#define HS_PIPE_STEP(RLOAD, RSTORE)                                                            \
+    {                                                                                          \
+        const int slot = (int)(s & 1);                                                         \
+        fetch_offsets(ach, bch);                                                               \
+        stage_load<C::UA, C::UB>(RLOAD, rsA, rsB, a_off, b_off, ach, bch);                     \
+        stage_scales();                                                                        \
+        __builtin_amdgcn_sched_barrier(0);                                                     \
+        mm_compute<FAM, FORM, BM, BN, CPS, WAVES>(                                             \
+            acc, ring + slot * C::STAGE, ring + slot * C::STAGE + C::A_STAGE, lane, wm, wn,    \
+            sa, sb, [&]() {                                                                    \
+                __builtin_amdgcn_sched_barrier(0);                                             \
+                stage_store<C::UA, C::UB, C::A_STAGE, C::NT>(RSTORE, ring + (slot ^ 1) * C::STAGE, tid); \
+                __builtin_amdgcn_sched_barrier(0);                                             \
+            });                                                                                \
+        __syncthreads();                                                                       \
+        if (++s >= nstages) break;                                                             \
+    }
+#elif HS_STORE_FIRST == 1
 #define HS_PIPE_STEP(RLOAD, RSTORE)                                                            \
     {                                                                                          \
         const int slot = (int)(s & 1);                                                         \
@@ -636,7 +695,7 @@ void mm_kernel(MainArgs a) {
         __builtin_amdgcn_sched_barrier(0);                                                     \
         mm_compute<FAM, FORM, BM, BN, CPS, WAVES>(acc, ring + slot * C::STAGE,                 \
                                            ring + slot * C::STAGE + C::A_STAGE, lane, wm, wn,  \
-                                           sa, sb);                                            \
+                                           sa, sb, []() {});                                   \
         __syncthreads();                                                                       \
         if (++s >= nstages) break;                                                             \
     }
@@ -650,7 +709,7 @@ void mm_kernel(MainArgs a) {
         __builtin_amdgcn_sched_barrier(0);                                                     \
         mm_compute<FAM, FORM, BM, BN, CPS, WAVES>(acc, ring + slot * C::STAGE,                 \
                                            ring + slot * C::STAGE + C::A_STAGE, lane, wm, wn,  \
-                                           sa, sb);                                            \
+                                           sa, sb, []() {});                                   \
         __builtin_amdgcn_sched_barrier(0);                                                     \
         stage_store<C::UA, C::UB, C::A_STAGE, C::NT>(RSTORE, ring + (slot ^ 1) * C::STAGE, tid); \
         __syncthreads();                                                                       \
@@ -828,7 +887,7 @@ static hipError_t launch_mm_t(const MainArgs &a, hipStream_t st) {
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    const int64_t nwg = (int64_t)a.p * a.GS * a.n_ntiles;
+    const int64_t nwg = (int64_t)a.K * a.n_ug * a.n_tg * a.grp_v * a.grp_t;
     hipLaunchKernelGGL((mm_kernel<FAM, FORM, BM, BN, CPS, WAVES>), dim3((unsigned)nwg), dim3(C::NT), 2 * C::STAGE, st, a);
     return hipGetLastError();
 }
@@ -859,8 +918,14 @@ hipError_t launch_mm(int fam, int form, const MainArgs &a, hipStream_t st) {
     if (fam == FAM_F16) return launch_mm_t<FAM_F16, 0, 256, 256, 2, HS_WAVES_B16>(a, st);
     if (fam == FAM_BF16 && form == 0) return launch_mm_t<FAM_BF16, 0, 256, 256, 2, HS_WAVES_B16>(a, st);
     if (fam == FAM_BF16 && form == 1) return launch_mm_t<FAM_BF16, 1, 256, 256, 1, HS_WAVES_SPLIT>(a, st);
-    if (fam == FAM_FP8 && form == 0) return launch_mm_t<FAM_FP8, 0, 256, 256, 2, 8>(a, st);
-    if (fam == FAM_FP8 && form == 1) return launch_mm_t<FAM_FP8, 1, 256, 256, 1, 8>(a, st);
+#ifndef HS_WAVES_FP8
+#define HS_WAVES_FP8 8
+#endif
+#ifndef HS_WAVES_FP8R
+#define HS_WAVES_FP8R 8
+#endif
+    if (fam == FAM_FP8 && form == 0) return launch_mm_t<FAM_FP8, 0, 256, 256, 2, HS_WAVES_FP8>(a, st);
+    if (fam == FAM_FP8 && form == 1) return launch_mm_t<FAM_FP8, 1, 256, 256, 1, HS_WAVES_FP8R>(a, st);
     return hipErrorInvalidValue;
 }
 
