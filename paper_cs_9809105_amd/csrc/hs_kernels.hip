@@ -330,6 +330,12 @@ struct MmCfg {
     static const int TM = WM / MT, TN = WN / MT;
     static const int STAGE = A_STAGE + B_STAGE;         // one slot of the LDS ring
     static const int LPS = UA + UB;                     // DMA loads per thread per stage
+#ifndef HS_B_DIRECT
+#define HS_B_DIRECT 1
+#endif
+    // B fragments straight from memory into registers (32x32 families)
+    static const bool BD = HS_B_DIRECT && FAM != FAM_F64 && FAM != FAM_FP8;
+    static const int LDS_BYTES = 2 * (BD ? A_STAGE : STAGE);   // two slots
 };
 
 // One pipeline stage of block products from LDS: for every chunk of the
@@ -447,6 +453,60 @@ DEVI void mm_compute(AccArr &acc, const uint8_t *Ab, const uint8_t *Bb, int lane
     }
 }
 
+// Fragment reads and MFMA tile products of the 32x32 families (FP32,
+// BF16, FP16, split-BF16) for the B-direct stage below.  Lane group g
+// = lane / 32 holds plane g of a chunk row (16 bytes); lane & 31 the row.
+template <int FAM, int FORM, int BM, int BN, int CPS, int WAVES, typename AV>
+DEVI void read_a_frags(AV &av, const uint8_t *Ab, int c, int mi, int lane, int wm) {
+    typedef MmCfg<FAM, FORM, BM, BN, CPS, WAVES> C;
+    const int r32 = lane & 31, g = lane >> 5;
+#pragma unroll
+    for (int P = 0; P < C::NP; ++P)
+        av[P] = *(const u32x4 *)(Ab + (P * CPS + c) * BM * C::CB + g * BM * 16 + (wm * C::WM + mi * 32 + r32) * 16);
+}
+
+template <int FAM, int FORM, int TN, typename AccRow, typename AV, typename BV>
+DEVI void mfma_row(AccRow &accr, const AV &av, const BV &bv) {
+#pragma unroll
+    for (int ni = 0; ni < TN; ++ni) {
+        if constexpr (FAM == FAM_F32) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                accr[ni] = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(av[0][t]), __uint_as_float(bv[0][ni][t]),
+                                                               accr[ni], 0, 0, 0);
+        } else if constexpr (FAM == FAM_F16) {
+            accr[ni] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, av[0]),
+                                                              __builtin_bit_cast(f16x8, bv[0][ni]), accr[ni], 0, 0, 0);
+        } else if constexpr (FORM == 0) {
+            accr[ni] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, av[0]),
+                                                               __builtin_bit_cast(bf16x8, bv[0][ni]), accr[ni], 0, 0, 0);
+        } else {
+#pragma unroll
+            for (int q = 0; q < 6; ++q) {
+                const int pa = q < 3 ? 2 - q : (q == 3 ? 1 : 0);
+                const int pb = q < 3 ? q : (q == 4 ? 1 : 0);
+                accr[ni] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, av[pa]),
+                                                                   __builtin_bit_cast(bf16x8, bv[pb][ni]), accr[ni], 0, 0, 0);
+            }
+        }
+    }
+}
+
+// One stage of a 32x32 family whose B fragments are already in registers
+// (bq[chunk][piece][column tile]); A fragments come from the LDS slot.
+template <int FAM, int FORM, int BM, int BN, int CPS, int WAVES, typename AccArr, typename BQ>
+DEVI void mm_compute_bd(AccArr &acc, const uint8_t *Ab, const BQ &bq, int lane, int wm) {
+    typedef MmCfg<FAM, FORM, BM, BN, CPS, WAVES> C;
+#pragma unroll
+    for (int c = 0; c < CPS; ++c)
+#pragma unroll
+        for (int mi = 0; mi < C::TM; ++mi) {
+            u32x4 av[C::NP];
+            read_a_frags<FAM, FORM, BM, BN, CPS, WAVES>(av, Ab, c, mi, lane, wm);
+            mfma_row<FAM, FORM, C::TN>(acc[mi], av, bq[c]);
+        }
+}
+
 // Buffer resource over a packed operand (raw buffer, byte addressed; the
 // third dword is the gfx9 default format word).
 DEVI __amdgpu_buffer_rsrc_t packed_rsrc(const uint8_t *base, uint32_t bytes) {
@@ -479,12 +539,25 @@ DEVI void stage_store(const u32x4 (&r)[UA + UB], uint8_t *slot, int tid) {
     for (int q = 0; q < UB; ++q) *(u32x4 *)(slot + A_STAGE + (tid + NT * q) * 16) = r[UA + q];
 }
 
+template <int UA>
+DEVI void stage_load_a(u32x4 (&r)[UA], __amdgpu_buffer_rsrc_t ra, const uint32_t (&a_off)[UA], uint32_t ach) {
+#pragma unroll
+    for (int q = 0; q < UA; ++q)
+        r[q] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(ra, (int)a_off[q], (int)ach, 0));
+}
+
+template <int UA, int NT>
+DEVI void stage_store_a(const u32x4 (&r)[UA], uint8_t *slot, int tid) {
+#pragma unroll
+    for (int q = 0; q < UA; ++q) *(u32x4 *)(slot + (tid + NT * q) * 16) = r[q];
+}
+
 template <int FAM, int FORM, int BM, int BN, int CPS, int WAVES>
 __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(WAVES / 4, WAVES / 4)))
 void mm_kernel(MainArgs a) {
     typedef MmCfg<FAM, FORM, BM, BN, CPS, WAVES> C;
     typedef typename Mfma<FAM>::Acc Acc;
-    extern __shared__ __attribute__((aligned(16))) uint8_t ring[];   // 2 * C::STAGE bytes
+    extern __shared__ __attribute__((aligned(16))) uint8_t ring[];   // C::LDS_BYTES
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -572,17 +645,26 @@ void mm_kernel(MainArgs a) {
     // of a residue class holds the same block at the same time.  cs counts
     // the stages inside a block.  Past the last stage the position stays put,
     // so the surplus fetches re-read the last stage (never used).
-    int kb = HS_CLASS_ORDER ? v % a.K : v, cs = 0, fetched = 0;
+    struct Pos { int kb, cs, fetched; };
+    const int kb0 = HS_CLASS_ORDER ? v % a.K : v;
     const uint32_t a_stage = (uint32_t)(MS * C::CB), b_stage = (uint32_t)(BN * C::CB);
+    // first chunk of the stage at q, then advance q by one stage
+    auto next_chunk = [&](Pos &q) -> uint32_t {
+        // wave-uniform by construction; readfirstlane keeps the stage
+        // offsets in SGPRs whatever the compiler's uniformity analysis finds
+        const uint32_t ch = (uint32_t)__builtin_amdgcn_readfirstlane((int)((uint32_t)q.kb * (uint32_t)nch + (uint32_t)(q.cs * CPS)));
+        if (++q.fetched < nstages && ++q.cs == spb) {   // next step: shift by K along the ring
+            q.cs = 0;
+            q.kb += K;
+            if (q.kb >= p) q.kb -= p;
+        }
+        return ch;
+    };
+    Pos pa{kb0, 0, 0};
     auto fetch_offsets = [&](uint32_t &ach, uint32_t &bch) {
-        const uint32_t ch = (uint32_t)kb * (uint32_t)nch + (uint32_t)(cs * CPS);
+        const uint32_t ch = next_chunk(pa);
         ach = ch * a_stage;
         bch = ch * b_stage;
-        if (++fetched < nstages && ++cs == spb) {   // next step: shift by K along the ring
-            cs = 0;
-            kb += K;
-            if (kb >= p) kb -= p;
-        }
     };
 
     // FP8: block-scale bytes of the stage being multiplied.  Every 32-row
@@ -647,80 +729,90 @@ void mm_kernel(MainArgs a) {
 #pragma unroll
         for (int ni = 0; ni < C::TN; ++ni) acc[mi][ni] = Acc{};
 
-    // Pipeline: the global loads for stage s + 2 are issued at the top of
-    // stage s into one of two register sets and land in LDS at the end of
-    // stage s + 1, so each fetch has two stages of MFMA work to arrive.
-    // LDS holds two slots: stage s is read from slot s % 2 while stage s + 1
-    // is written into the other one.
-    u32x4 r0[C::LPS], r1[C::LPS];
     uint32_t ach, bch;
-    fetch_offsets(ach, bch);
-    stage_load<C::UA, C::UB>(r0, rsA, rsB, a_off, b_off, ach, bch);
-    fetch_offsets(ach, bch);
-    stage_load<C::UA, C::UB>(r1, rsA, rsB, a_off, b_off, ach, bch);
-    stage_store<C::UA, C::UB, C::A_STAGE, C::NT>(r0, ring, tid);
-    __syncthreads();
-#ifndef HS_STORE_FIRST
-#define HS_STORE_FIRST 1
-#endif
-#if HS_STORE_FIRST == 2
-    // The LDS image of stage s + 1 (loaded a stage earlier) is written during
-    // stage s, after the first row tile's MFMAs are issued, so the writes
-    // overlap MFMAs; the barrier closes the stage.
-#define HS_PIPE_STEP(RLOAD, RSTORE)                                                            \
+    if constexpr (C::BD) {
+        // The travelling operand skips LDS: each wave loads its own MFMA
+        // fragments of B (the packed layout already is the fragment layout:
+        // 32 lanes read 512 contiguous bytes of one plane) one stage ahead,
+        // into one of two register sets.  Only the K static blocks go
+        // through LDS (two slots, loaded two stages ahead, written one
+        // stage ahead, one barrier per stage), which halves the LDS writes
+        // and cuts the LDS reads by a third.
+        const int r32 = lane & 31, g = lane >> 5;
+        const uint32_t b_lane = (uint32_t)(ntile * (int64_t)p * nch * BN * C::CB + (int64_t)g * BN * 16 +
+                                           (int64_t)(wn * C::WN + r32) * 16);
+        const uint32_t b_piece = (uint32_t)a.b_piece;
+        typedef u32x4 BQ[CPS][C::NP][C::TN];
+        auto load_b = [&](BQ &bq, uint32_t ch) {
+            const uint32_t bst = ch * b_stage;
+#pragma unroll
+            for (int c = 0; c < CPS; ++c)
+#pragma unroll
+                for (int P = 0; P < C::NP; ++P)
+#pragma unroll
+                    for (int ni = 0; ni < C::TN; ++ni)
+                        bq[c][P][ni] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(
+                            rsB, (int)(b_lane + ni * 32 * 16), (int)(bst + P * b_piece + c * BN * C::CB), 0));
+        };
+        u32x4 r0[C::UA], r1[C::UA];
+        BQ q0, q1;
+        Pos pb{kb0, 0, 0};
+        fetch_offsets(ach, bch);
+        stage_load_a<C::UA>(r0, rsA, a_off, ach);
+        fetch_offsets(ach, bch);
+        stage_load_a<C::UA>(r1, rsA, a_off, ach);
+        load_b(q0, next_chunk(pb));
+        stage_store_a<C::UA, C::NT>(r0, ring, tid);
+        __syncthreads();
+#define HS_PIPE_STEP(RLOAD, RSTORE, QUSE, QLOAD)                                               \
     {                                                                                          \
         const int slot = (int)(s & 1);                                                         \
         fetch_offsets(ach, bch);                                                               \
-        stage_load<C::UA, C::UB>(RLOAD, rsA, rsB, a_off, b_off, ach, bch);                     \
-        stage_scales();                                                                        \
+        stage_load_a<C::UA>(RLOAD, rsA, a_off, ach);                                           \
+        load_b(QLOAD, next_chunk(pb));                                                         \
+        stage_store_a<C::UA, C::NT>(RSTORE, ring + (slot ^ 1) * C::A_STAGE, tid);              \
         __builtin_amdgcn_sched_barrier(0);                                                     \
-        mm_compute<FAM, FORM, BM, BN, CPS, WAVES>(                                             \
-            acc, ring + slot * C::STAGE, ring + slot * C::STAGE + C::A_STAGE, lane, wm, wn,    \
-            sa, sb, [&]() {                                                                    \
-                __builtin_amdgcn_sched_barrier(0);                                             \
-                stage_store<C::UA, C::UB, C::A_STAGE, C::NT>(RSTORE, ring + (slot ^ 1) * C::STAGE, tid); \
-                __builtin_amdgcn_sched_barrier(0);                                             \
-            });                                                                                \
+        mm_compute_bd<FAM, FORM, BM, BN, CPS, WAVES>(acc, ring + slot * C::A_STAGE, QUSE, lane, wm); \
         __syncthreads();                                                                       \
         if (++s >= nstages) break;                                                             \
     }
-#elif HS_STORE_FIRST == 1
-#define HS_PIPE_STEP(RLOAD, RSTORE)                                                            \
-    {                                                                                          \
-        const int slot = (int)(s & 1);                                                         \
-        fetch_offsets(ach, bch);                                                               \
-        stage_load<C::UA, C::UB>(RLOAD, rsA, rsB, a_off, b_off, ach, bch);                     \
-        stage_store<C::UA, C::UB, C::A_STAGE, C::NT>(RSTORE, ring + (slot ^ 1) * C::STAGE, tid); \
-        stage_scales();                                                                        \
-        __builtin_amdgcn_sched_barrier(0);                                                     \
-        mm_compute<FAM, FORM, BM, BN, CPS, WAVES>(acc, ring + slot * C::STAGE,                 \
-                                           ring + slot * C::STAGE + C::A_STAGE, lane, wm, wn,  \
-                                           sa, sb, []() {});                                   \
-        __syncthreads();                                                                       \
-        if (++s >= nstages) break;                                                             \
-    }
-#else
-#define HS_PIPE_STEP(RLOAD, RSTORE)                                                            \
-    {                                                                                          \
-        const int slot = (int)(s & 1);                                                         \
-        fetch_offsets(ach, bch);                                                               \
-        stage_load<C::UA, C::UB>(RLOAD, rsA, rsB, a_off, b_off, ach, bch);                     \
-        stage_scales();                                                                        \
-        __builtin_amdgcn_sched_barrier(0);                                                     \
-        mm_compute<FAM, FORM, BM, BN, CPS, WAVES>(acc, ring + slot * C::STAGE,                 \
-                                           ring + slot * C::STAGE + C::A_STAGE, lane, wm, wn,  \
-                                           sa, sb, []() {});                                   \
-        __builtin_amdgcn_sched_barrier(0);                                                     \
-        stage_store<C::UA, C::UB, C::A_STAGE, C::NT>(RSTORE, ring + (slot ^ 1) * C::STAGE, tid); \
-        __syncthreads();                                                                       \
-        if (++s >= nstages) break;                                                             \
-    }
-#endif
-    for (int s = 0; s < nstages;) {
-        HS_PIPE_STEP(r0, r1)
-        HS_PIPE_STEP(r1, r0)
-    }
+        for (int s = 0; s < nstages;) {
+            HS_PIPE_STEP(r0, r1, q0, q1)
+            HS_PIPE_STEP(r1, r0, q1, q0)
+        }
 #undef HS_PIPE_STEP
+    } else {
+        // Both operands through LDS, two slots: the global loads for stage
+        // s + 2 are issued at the top of stage s into one of two register
+        // sets; the LDS image of stage s + 1 is written into the other slot
+        // at the top of stage s, and one barrier closes each stage.
+        u32x4 r0[C::LPS], r1[C::LPS];
+        fetch_offsets(ach, bch);
+        stage_load<C::UA, C::UB>(r0, rsA, rsB, a_off, b_off, ach, bch);
+        fetch_offsets(ach, bch);
+        stage_load<C::UA, C::UB>(r1, rsA, rsB, a_off, b_off, ach, bch);
+        stage_store<C::UA, C::UB, C::A_STAGE, C::NT>(r0, ring, tid);
+        __syncthreads();
+#define HS_PIPE_STEP(RLOAD, RSTORE)                                                            \
+    {                                                                                          \
+        const int slot = (int)(s & 1);                                                         \
+        fetch_offsets(ach, bch);                                                               \
+        stage_load<C::UA, C::UB>(RLOAD, rsA, rsB, a_off, b_off, ach, bch);                     \
+        stage_store<C::UA, C::UB, C::A_STAGE, C::NT>(RSTORE, ring + (slot ^ 1) * C::STAGE, tid); \
+        stage_scales();                                                                        \
+        __builtin_amdgcn_sched_barrier(0);                                                     \
+        mm_compute<FAM, FORM, BM, BN, CPS, WAVES>(acc, ring + slot * C::STAGE,                 \
+                                           ring + slot * C::STAGE + C::A_STAGE, lane, wm, wn,  \
+                                           sa, sb, []() {});                                   \
+        __syncthreads();                                                                       \
+        if (++s >= nstages) break;                                                             \
+    }
+        for (int s = 0; s < nstages;) {
+            HS_PIPE_STEP(r0, r1)
+            HS_PIPE_STEP(r1, r0)
+        }
+#undef HS_PIPE_STEP
+    }
 
     // epilogue: partial l of the tile row rho goes to output stripe (v - l).
     // One tile row at a time (row index computed once, then its columns).
@@ -883,12 +975,12 @@ static hipError_t launch_mm_t(const MainArgs &a, hipStream_t st) {
     static bool attr_set = false;
     if (!attr_set) {
         hipError_t e = hipFuncSetAttribute((const void *)mm_kernel<FAM, FORM, BM, BN, CPS, WAVES>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 2 * C::STAGE);
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, C::LDS_BYTES);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
     const int64_t nwg = (int64_t)a.K * a.n_ug * a.n_tg * a.grp_v * a.grp_t;
-    hipLaunchKernelGGL((mm_kernel<FAM, FORM, BM, BN, CPS, WAVES>), dim3((unsigned)nwg), dim3(C::NT), 2 * C::STAGE, st, a);
+    hipLaunchKernelGGL((mm_kernel<FAM, FORM, BM, BN, CPS, WAVES>), dim3((unsigned)nwg), dim3(C::NT), C::LDS_BYTES, st, a);
     return hipGetLastError();
 }
 
