@@ -171,8 +171,9 @@ hs_status hs_gemm_backward(int64_t m, int64_t n, int64_t k, hs_dtype dtype, hs_s
                            void *ws, size_t ws_bytes, void *stream);
 
 /* Kernel timing for measurement.  Between hs_profile_begin() and
- * hs_profile_end(), every launch of the main (MFMA) kernel of any call made
- * from this process is bracketed by a pair of HIP events on its stream.
+ * hs_profile_end(), every launch of the main kernel of any call made from
+ * this process (the MFMA kernel of a product, the matrix-vector kernel of
+ * hs_gemv) is bracketed by a pair of HIP events on its stream.
  * hs_profile_end() waits for those events and returns the summed elapsed
  * milliseconds and the number of launches.  Not thread-safe; host only.
  * Returns HS_ERR_INVALID_VALUE if profiling was not begun. */

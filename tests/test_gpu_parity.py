@@ -370,3 +370,88 @@ def test_fp8_r1_config_16384():
     eB = err_row(host(dB)[rk], oracle.grad_b_rows(A64, G64, rk))
     print("fp8 r1 16384: err_row C %.3e dA %.3e dB %.3e err_elem C %.3e" % (eC, eA, eB, eCe))
     assert max(eC, eA, eB) <= 1e-2 and eCe <= FP8_R1_ELEM
+
+
+# ---------------------------------------------------------------------------
+# The pieces themselves.  A product with a diagonal (or identity) operand
+# has one nonzero term per output element, so the output shows each
+# element's split or quantisation, for both operand roles and every
+# orientation (NN, TN, and NT through the backward call).  The diagonal
+# holds signed powers of two, so every partial sum is exact whatever the
+# MFMA's internal alignment and rounding (which differ from a sequence of
+# IEEE FP32 additions); the split is then pinned by exact reconstruction,
+# a = a0 + a1 + a2, and the quantisation by oracle.precision bit for bit.
+# ---------------------------------------------------------------------------
+def _pow2_diag(n, seed):
+    g = np.random.default_rng(seed)
+    d = g.choice([-1.0, 1.0], n) * 2.0 ** g.integers(-6, 7, n)
+    return np.diag(d), d
+
+
+@pytest.mark.parametrize("tn", [False, True])
+def test_split3_pieces_reconstruct_exactly(tn):
+    _skip_no_gpu()
+    m, k, p = 200, 320, 4
+    A, Af = to_dev(inputs.row_scaled((k, m) if tn else (m, k), seed=901), "split3_bf16")
+    D64, d = _pow2_diag(k, 902)
+    D, _ = to_dev(D64, "split3_bf16")
+    note("split pieces, static side, tn=%s" % tn)
+    C = (hs.hs_gemm_tn if tn else hs.hs_gemm)(A, D, dtype="split3_bf16", p=p, K=2)
+    Aop = Af.T if tn else Af                       # the operand as it multiplies
+    assert np.array_equal(host(C), Aop * d[None, :])
+    # travelling side: diag(d) . B
+    B, Bf = to_dev(inputs.row_scaled((k, m), seed=903), "split3_bf16")
+    note("split pieces, travelling side, tn=%s" % tn)
+    C2 = (hs.hs_gemm_tn if tn else hs.hs_gemm)(D, B, dtype="split3_bf16", p=p, K=2)
+    assert np.array_equal(host(C2), d[:, None] * Bf)
+
+
+def test_split3_pieces_reconstruct_exactly_backward():
+    """dA = G . B^T (NT) with B diagonal, dB = A^T . G (TN) with A diagonal."""
+    _skip_no_gpu()
+    n = 256
+    G, Gf = to_dev(inputs.row_scaled((n, n), seed=904), "split3_bf16")
+    DA64, da = _pow2_diag(n, 905)
+    DB64, db = _pow2_diag(n, 906)
+    DA, _ = to_dev(DA64, "split3_bf16")
+    DB, _ = to_dev(DB64, "split3_bf16")
+    note("split pieces, backward")
+    dA, dB = hs.hs_gemm_backward(DA, DB, G, dtype="split3_bf16", p=4, K=2)
+    assert np.array_equal(host(dA), Gf * db[None, :])
+    assert np.array_equal(host(dB), da[:, None] * Gf)
+
+
+@pytest.mark.parametrize("dt", FP8)
+@pytest.mark.parametrize("tn", [False, True])
+def test_fp8_quantisation_bit_exact(dt, tn):
+    """A . I and I . B return the dequantised operand exactly (products with
+    an exact 1 and at most one nonzero term per element)."""
+    _skip_no_gpu()
+    from oracle import precision as P
+    refine = dt == "fp8_e4m3_r1"
+    m, k, p = 256, 384, 2
+    A, Af = to_dev(inputs.row_scaled((k, m) if tn else (m, k), seed=911), dt)
+    I_k, _ = to_dev(np.eye(k), dt)
+    note("fp8 quantisation, static side", dt, tn)
+    C = (hs.hs_gemm_tn if tn else hs.hs_gemm)(A, I_k, dtype=dt, p=p)
+    Aop = P.fp8_dequantized(Af, refine)            # 128 x 128 tiles from the origin
+    assert np.array_equal(host(C), Aop.T if tn else Aop)
+    B, Bf = to_dev(inputs.row_scaled((m, k), seed=912), dt)
+    I_m, _ = to_dev(np.eye(m), dt)
+    note("fp8 quantisation, travelling side", dt, tn)
+    C2 = (hs.hs_gemm_tn if tn else hs.hs_gemm)(I_m, B, dtype=dt, p=p)
+    assert np.array_equal(host(C2), P.fp8_dequantized(Bf, refine))
+
+
+@pytest.mark.parametrize("dt", FP8)
+def test_fp8_quantisation_bit_exact_backward(dt):
+    _skip_no_gpu()
+    from oracle import precision as P
+    n = 256
+    G, Gf = to_dev(inputs.row_scaled((n, n), seed=913), dt)
+    I, _ = to_dev(np.eye(n), dt)
+    note("fp8 quantisation, backward", dt)
+    dA, dB = hs.hs_gemm_backward(I, I, G, dtype=dt, p=2)
+    ref = P.fp8_dequantized(Gf, dt == "fp8_e4m3_r1")
+    assert np.array_equal(host(dA), ref)
+    assert np.array_equal(host(dB), ref)
