@@ -388,6 +388,7 @@ hs_status hs_gemv(int64_t m, int64_t n, hs_dtype dtype, hs_schedule s,
     g.p = r.p; g.K = r.K; g.Kt = r.p / r.K;
     g.S_r = std::max<int64_t>(1, ceil_div(m, r.p));
     g.S_k = std::max<int64_t>(1, ceil_div(n, r.p));
+    if (g.S_k * r.p >= ((int64_t)1 << 31)) return HS_ERR_NOT_SUPPORTED;   // 32-bit positions
     const int VE = f64 ? 2 : 4;
     g.vec = (g.S_k % VE == 0 && lda % VE == 0 && n % VE == 0 && aligned(A, 16) && aligned(x, 16)) ? 1 : 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;

@@ -23,6 +23,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "hs_internal.h"
 
 namespace hs {
@@ -342,14 +344,9 @@ struct MmCfg {
 // stage, the wave's MFMA tiles accumulate A_rows x B_cols.
 // For FP8, sa[c][P][mi] / sb[c][P][ni] are the E8M0 block-scale bytes of
 // chunk c, piece P, row / column tile (uniform across the wave).
-//
-// `mid` runs once, right after the MFMAs of the first row tile of the first
-// chunk are issued: the pipeline puts the LDS writes of the next stage there,
-// so they overlap MFMAs instead of delaying this stage's first LDS reads.
-template <int FAM, int FORM, int BM, int BN, int CPS, int WAVES, typename AccArr, typename SA, typename SB,
-          typename Mid>
+template <int FAM, int FORM, int BM, int BN, int CPS, int WAVES, typename AccArr, typename SA, typename SB>
 DEVI void mm_compute(AccArr &acc, const uint8_t *Ab, const uint8_t *Bb, int lane, int wm, int wn,
-                     const SA &sa, const SB &sb, Mid &&mid) {
+                     const SA &sa, const SB &sb) {
     typedef MmCfg<FAM, FORM, BM, BN, CPS, WAVES> C;
 #pragma unroll
     for (int c = 0; c < CPS; ++c) {
@@ -387,7 +384,6 @@ DEVI void mm_compute(AccArr &acc, const uint8_t *Ab, const uint8_t *Bb, int lane
                     acc[mi][ni] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
                         av[0], bv[0][ni], acc[mi][ni], 0, 0, 0, sa[c][0][mi], 0, sb[c][0][ni]);
                 }
-                if (c == 0 && mi == 0) mid();
             }
         } else if constexpr (FAM == FAM_F64) {
             const int r16 = lane & 15, g = lane >> 4;
@@ -403,7 +399,6 @@ DEVI void mm_compute(AccArr &acc, const uint8_t *Ab, const uint8_t *Bb, int lane
 #pragma unroll
                 for (int ni = 0; ni < C::TN; ++ni)
                     acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[mi], bv[ni], acc[mi][ni], 0, 0, 0);
-            if (c == 0) mid();
         } else {
             const int r32 = lane & 31, g = lane >> 5;
             // all B fragments of the chunk, then one row tile of A at a time
@@ -447,7 +442,6 @@ DEVI void mm_compute(AccArr &acc, const uint8_t *Ab, const uint8_t *Bb, int lane
                         }
                     }
                 }
-                if (c == 0 && mi == 0) mid();
             }
         }
     }
@@ -803,7 +797,7 @@ void mm_kernel(MainArgs a) {
         __builtin_amdgcn_sched_barrier(0);                                                     \
         mm_compute<FAM, FORM, BM, BN, CPS, WAVES>(acc, ring + slot * C::STAGE,                 \
                                            ring + slot * C::STAGE + C::A_STAGE, lane, wm, wn,  \
-                                           sa, sb, []() {});                                   \
+                                           sa, sb);                                            \
         __syncthreads();                                                                       \
         if (++s >= nstages) break;                                                             \
     }
@@ -899,42 +893,63 @@ __global__ __launch_bounds__(256) void fill_zero_kernel(OT *Cout, int64_t M, int
 // ---------------------------------------------------------------------------
 template <typename T, int VE>
 __global__ __launch_bounds__(256) void gemv_kernel(GemvArgs a) {
+    typedef typename std::conditional<VE == 4, float4, typename std::conditional<VE == 2, double2, T>::type>::type V;
+    constexpr int U = 4;                       // loads in flight per lane
     const int lane = threadIdx.x & 63;
     const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (row >= a.m) return;
     const T *Ar = (const T *)a.A + row * a.lda;
     const T *x = (const T *)a.x;
-    const int64_t rs = row / a.S_r;
-    const int64_t S_k = a.S_k;
-    const int64_t total = (int64_t)a.Kt * S_k;
+    const int p = a.p, K = a.K;
+    const int rs = (int)(row / a.S_r);
+    const int S_k = (int)a.S_k;                // host: S_k * p fits in 32 bits
+    const int total = a.Kt * S_k;
     double S = 0.0;
-    for (int l = a.K - 1; l >= 0; --l) {      // collector: c^{K-1} first
-        const int64_t v = (rs + l) % a.p;      // the virtual processor holding partial l
+    for (int l = K - 1; l >= 0; --l) {         // collector: c^{K-1} first
+        const int v = (rs + l) % p;            // the virtual processor holding partial l
+        // lane position: element e of the partial's sequence lies in step
+        // j = e / S_k (block kb = (v + j K) mod p) at offset e mod S_k
+        int e = lane * VE, j = e / S_k, off = e % S_k;
+        int kb = (int)(((int64_t)v + (int64_t)j * K) % p);
+        auto advance = [&]() {
+            e += 64 * VE;
+            off += 64 * VE;
+            while (off >= S_k) {
+                off -= S_k;
+                kb += K;
+                if (kb >= p) kb -= p;
+            }
+        };
         T acc = 0;
-        int64_t e0 = (int64_t)lane * VE;
-        int64_t j = e0 / S_k, off = e0 % S_k;
-        for (int64_t e = e0; e < total; e += 64 * VE) {
-            const int64_t kb = (v + j * a.K) % a.p;   // block held at step j
-            const int64_t col = kb * S_k + off;
-            if (col < a.n) {
-                if constexpr (VE == 4) {
-                    const float4 av = *(const float4 *)(Ar + col);
-                    const float4 xv = *(const float4 *)(x + col);
-                    acc += av.x * xv.x;
-                    acc += av.y * xv.y;
-                    acc += av.z * xv.z;
-                    acc += av.w * xv.w;
-                } else if constexpr (VE == 2) {
-                    const double2 av = *(const double2 *)(Ar + col);
-                    const double2 xv = *(const double2 *)(x + col);
-                    acc += av.x * xv.x;
-                    acc += av.y * xv.y;
+        while (e < total) {
+            V av[U], xv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t col = (int64_t)kb * S_k + off;
+                const bool ok = e < total && col < a.n;
+                if (ok) {
+                    av[u] = *(const V *)(Ar + col);
+                    xv[u] = *(const V *)(x + col);
                 } else {
-                    acc += Ar[col] * x[col];
+                    av[u] = V{};
+                    xv[u] = V{};
+                }
+                advance();
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if constexpr (VE == 4) {
+                    acc += av[u].x * xv[u].x;
+                    acc += av[u].y * xv[u].y;
+                    acc += av[u].z * xv[u].z;
+                    acc += av[u].w * xv[u].w;
+                } else if constexpr (VE == 2) {
+                    acc += av[u].x * xv[u].x;
+                    acc += av[u].y * xv[u].y;
+                } else {
+                    acc += av[u] * xv[u];
                 }
             }
-            off += 64 * VE;
-            while (off >= S_k) { off -= S_k; ++j; }
         }
 #pragma unroll
         for (int m = 32; m >= 1; m >>= 1) acc += __shfl_xor(acc, m, 64);
@@ -972,12 +987,16 @@ hipError_t launch_pack(int kind, int kmajor, const PackArgs &a, hipStream_t st) 
 template <int FAM, int FORM, int BM, int BN, int CPS, int WAVES>
 static hipError_t launch_mm_t(const MainArgs &a, hipStream_t st) {
     typedef MmCfg<FAM, FORM, BM, BN, CPS, WAVES> C;
-    static bool attr_set = false;
-    if (!attr_set) {
+    // the dynamic LDS limit is a per-device function attribute: set it once
+    // on each device the kernel runs on (setting it twice is harmless)
+    static bool attr_set[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = -1;
+    if (dev < 0 || dev >= 64 || !attr_set[dev]) {
         hipError_t e = hipFuncSetAttribute((const void *)mm_kernel<FAM, FORM, BM, BN, CPS, WAVES>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, C::LDS_BYTES);
         if (e != hipSuccess) return e;
-        attr_set = true;
+        if (dev >= 0 && dev < 64) attr_set[dev] = true;
     }
     const int64_t nwg = (int64_t)a.K * a.n_ug * a.n_tg * a.grp_v * a.grp_t;
     hipLaunchKernelGGL((mm_kernel<FAM, FORM, BM, BN, CPS, WAVES>), dim3((unsigned)nwg), dim3(C::NT), C::LDS_BYTES, st, a);
