@@ -45,9 +45,10 @@ def parse():
                     help="target CPU time of the oracle baseline sample (0 to skip)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one plain 256 MiB device copy first (reference for HBM counters)")
-    ap.add_argument("--workload", default="step", choices=["step", "gemv"],
+    ap.add_argument("--workload", default="step", choices=["step", "gemv", "complex"],
                     help="step: the fwd+bwd product step (default); gemv: y = A.x alone "
-                         "(A n x n FP32, HBM-bound; reports GB/s)")
+                         "(A n x n FP32, HBM-bound; reports GB/s); complex: C = A.B on n x n "
+                         "complex64 N(0,1) data (--form c32_split3_bf16 or c32, compared with c32)")
     return ap.parse_args()
 
 
@@ -196,6 +197,74 @@ def gemv_main(args):
         "cpu_baseline": cpu}))
 
 
+def complex_main(args):
+    """C = A . B on n x n complex64 data: one product per step (forward),
+    run as the real product of A (n x 2n) and the 2 x 2 block embedding of B
+    (2n x 2n); 8 n^3 useful real flops."""
+    import numpy as np
+    import torch
+    import paper_cs_9809105_amd as hs
+    from paper_cs_9809105_amd import inputs
+    n, p, K = args.n, args.p, args.K
+    form = args.form if args.form.startswith("c32") else "c32_split3_bf16"
+    g = inputs.normal
+    A64 = g((n, n), inputs.BASE_SEED + 20) + 1j * g((n, n), inputs.BASE_SEED + 21)
+    B64 = g((n, n), inputs.BASE_SEED + 22) + 1j * g((n, n), inputs.BASE_SEED + 23)
+    A = torch.from_numpy(A64.astype(np.complex64)).cuda()
+    B = torch.from_numpy(B64.astype(np.complex64)).cuda()
+    C = torch.empty(n, n, dtype=torch.complex64, device="cuda")
+
+    def timed(fm, steps, warmup):
+        for _ in range(warmup):
+            hs.hs_gemm(A, B, dtype=fm, p=p, K=K, out=C)
+        torch.cuda.synchronize()
+        hs.hs_profile_begin()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            hs.hs_gemm(A, B, dtype=fm, p=p, K=K, out=C)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms, launches = hs.hs_profile_end()
+        return wall, ms / max(launches, 1)
+
+    useful = 8.0 * n ** 3
+    wall, avg = timed(form, args.steps, args.warmup)
+    mfma = (6 if form == "c32_split3_bf16" else 1) * useful
+    peak = PEAK["bf16" if form == "c32_split3_bf16" else "f32"]
+    achieved = mfma / (avg * 1e-3) / 1e12
+    comparison = None
+    if args.compare and form != "c32":
+        w2, a2 = timed("c32", max(2, args.steps // 2), 1)
+        comparison = {"c32": {"value": useful * max(2, args.steps // 2) / w2 / 1e12, "avg_main_kernel_ms": a2}}
+    cpu = None
+    if args.cpu_seconds > 0:
+        import oracle
+        Ah = A.cpu().numpy().astype(np.complex128)
+        Bh = B.cpu().numpy().astype(np.complex128)
+        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        t0 = time.perf_counter()
+        oracle.complex_gemm_rows(Ah, Bh, inputs.sample_rows(n, cores, seed=7))
+        t_cal = time.perf_counter() - t0
+        nrows = max(cores, min(n, int(cores * args.cpu_seconds / max(t_cal, 1e-6)) // cores * cores))
+        t0 = time.perf_counter()
+        oracle.complex_gemm_rows(Ah, Bh, inputs.sample_rows(n, nrows, seed=8))
+        dt = time.perf_counter() - t0
+        cpu = {"value": 8.0 * nrows * n * n / dt / 1e12, "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
+               "sample": "%d sampled rows of C (n=%d complex, FP64 parts, %.1f s)" % (nrows, n, dt)}
+    print(json.dumps({
+        "metric": "TFLOP/s of the complex product C = A.B (n=%d complex64): %s" % (n, form),
+        "value": useful * args.steps / wall / 1e12, "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": wall * 1e3 / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16x3" if form == "c32_split3_bf16" else "f32",
+        "data": "synthetic",
+        "config": {"workload": "hyper-systolic complex product, square n=%d, N(0,1) real and imaginary parts" % n,
+                   "M": n, "Kd": n, "N": n, "p": p, "K": K, "form": form},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None, "kernel": "mm_kernel (main MFMA loop)",
+                     "avg_kernel_ms": avg, "launches": args.steps},
+        "comparison": comparison, "cpu_baseline": cpu}))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -204,6 +273,8 @@ def main():
         sys.exit(2)
     if args.workload == "gemv":
         return gemv_main(args)
+    if args.workload == "complex":
+        return complex_main(args)
     import numpy as np
     import torch
     import paper_cs_9809105_amd as hs

@@ -76,7 +76,18 @@ extern "C" {
  *                  FP8 MFMA product with hardware block scales.
  *  HS_FP8_E4M3_R1  in f32,  out f32.  One refinement step: a ~= (q0 + q1/s1)/s
  *                  with q1 = e4m3((a s - q0) s1), s1 a power of two per tile;
- *                  products q0 q0', q0 q1', q1 q0'. */
+ *                  products q0 q0', q0 q1', q1 q0'.
+ *  HS_C32          in complex64, out complex64 (interleaved re, im FP32
+ *                  pairs; ld* in complex elements).  hs_gemm only.  The
+ *                  complex product (the complex-data workload of Sec. 7) as
+ *                  one real product on FP32 MFMA: A read as an m x 2k real
+ *                  matrix, B embedded as the 2k x 2n real matrix whose
+ *                  2 x 2 block (t, j) is [[re, im], [-im, re]] of b_tj, C
+ *                  written as m x 2n = interleaved complex.  4 real
+ *                  multiplications per complex one (no 3M rewrite: it
+ *                  cancels).
+ *  HS_C32_SPLIT3_BF16  the same with the split-BF16 arithmetic of
+ *                  HS_SPLIT3_BF16 (FP32-accurate).  hs_gemm only. */
 typedef enum {
     HS_F64 = 0,
     HS_F32 = 1,
@@ -84,7 +95,9 @@ typedef enum {
     HS_F16 = 3,
     HS_SPLIT3_BF16 = 4,
     HS_FP8_E4M3 = 5,
-    HS_FP8_E4M3_R1 = 6
+    HS_FP8_E4M3_R1 = 6,
+    HS_C32 = 7,
+    HS_C32_SPLIT3_BF16 = 8
 } hs_dtype;
 
 typedef enum {
@@ -134,7 +147,10 @@ size_t hs_workspace_size(hs_op op, int64_t m, int64_t n, int64_t k,
 
 /* C[m, n] = A[m, k] . B[k, n]  (Eq. PRODUCT; Algorithm HYPER-SYSTOLIC).
  * A: m x k, lda >= k.  B: k x n, ldb >= n.  C: m x n, ldc >= n (written,
- * never read).  All dtypes.  m, n or k may be 0 (k == 0 writes zeros). */
+ * never read).  All dtypes, the complex ones included (m, n, k and ld* then
+ * count complex elements; pointers 8-byte aligned).  m, n or k may be 0
+ * (k == 0 writes zeros).  hs_workspace_size(HS_OP_GEMM, m, n, k, ...) of a
+ * complex dtype is that of the real product m x 2k times 2k x 2n. */
 hs_status hs_gemm(int64_t m, int64_t n, int64_t k, hs_dtype dtype, hs_schedule s,
                   const void *A, int64_t lda, const void *B, int64_t ldb,
                   void *C, int64_t ldc, void *ws, size_t ws_bytes, void *stream);

@@ -7,7 +7,8 @@ binding) never touches it, and the two share no code.
 What it computes is the plain definition the method reaches exactly
 (Sec. 3.1, Eq. PRODUCT): c_ij = sum_k a_ik b_kj in double precision, ascending
 k, plus the transposed product, the matrix-vector product and the gradient of
-L = sum(C * G).  See ``hs_oracle.c``.  ``ring`` holds a literal simulator of
+L = sum(C * G), and the complex product (``complex_gemm``, by its real
+and imaginary parts).  See ``hs_oracle.c``.  ``ring`` holds a literal simulator of
 Algorithms SYSTOLIC and HYPER-SYSTOLIC (Sec. 5) and ``bases`` the regular
 hyper-systolic bases (Sec. 4.4, Sec. 5.2.1); both pin the schedule.
 
@@ -146,3 +147,25 @@ def grad_a_rows(G, B, rows):
 def grad_b_rows(A, G, rows):
     """Rows ``rows`` of dB = A^T . G (A m x k, G m x n)."""
     return gemm_tn_rows(A, G, rows)
+
+
+# ---------------------------------------------------------------------------
+# complex data (the complex workload of Sec. 7): the same definition,
+# c_ij = sum_k a_ik b_kj, in complex arithmetic, written with real products:
+# re c = re a re b - im a im b, im c = re a im b + im a re b.
+# ---------------------------------------------------------------------------
+def complex_gemm(A, B):
+    """C = A . B for complex A (m x k), B (k x n), in FP64 parts."""
+    A = np.asarray(A, np.complex128)
+    B = np.asarray(B, np.complex128)
+    Ar, Ai, Br, Bi = A.real, A.imag, B.real, B.imag
+    return (gemm(Ar, Br) - gemm(Ai, Bi)) + 1j * (gemm(Ar, Bi) + gemm(Ai, Br))
+
+
+def complex_gemm_rows(A, B, rows):
+    """Rows ``rows`` of the complex product A . B."""
+    A = np.asarray(A, np.complex128)
+    B = np.asarray(B, np.complex128)
+    Ar, Ai, Br, Bi = A.real, A.imag, B.real, B.imag
+    return ((gemm_rows(Ar, Br, rows) - gemm_rows(Ai, Bi, rows))
+            + 1j * (gemm_rows(Ar, Bi, rows) + gemm_rows(Ai, Br, rows)))

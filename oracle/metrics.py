@@ -9,9 +9,15 @@ err_elem = max_ij |C_ij - Chat_ij| / (|A| |B|)_ij
 import numpy as np
 
 
+def _promote(C, ref):
+    """float64, or complex128 when either side is complex (the imaginary
+    parts must count)."""
+    dt = np.complex128 if (np.iscomplexobj(C) or np.iscomplexobj(ref)) else np.float64
+    return np.asarray(C, dt), np.asarray(ref, dt)
+
+
 def err_row(C, ref):
-    C = np.asarray(C, np.float64)
-    ref = np.asarray(ref, np.float64)
+    C, ref = _promote(C, ref)
     if C.ndim == 1:
         C, ref = C[None, :], ref[None, :]
     num = np.linalg.norm(C - ref, axis=1)
@@ -21,7 +27,6 @@ def err_row(C, ref):
 
 
 def err_elem(C, ref, absprod):
-    C = np.asarray(C, np.float64)
-    ref = np.asarray(ref, np.float64)
+    C, ref = _promote(C, ref)
     den = np.where(absprod == 0, 1.0, absprod)
     return float(np.max(np.abs(C - ref) / den)) if C.size else 0.0

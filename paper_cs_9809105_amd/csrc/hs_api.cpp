@@ -54,6 +54,13 @@ bool form_info(hs_dtype dt, FormInfo *f) {
     }
 }
 
+// The complex dtypes run as one real product of their base form.
+bool complex_base(hs_dtype dt, hs_dtype *base) {
+    if (dt == HS_C32) { *base = HS_F32; return true; }
+    if (dt == HS_C32_SPLIT3_BF16) { *base = HS_SPLIT3_BF16; return true; }
+    return false;
+}
+
 // Default K: the divisor of p minimising the shift count K + p/K - 1
 // (Thm. on minimal length, Sec. 4.4); ties go to the smaller K.
 int default_K(int p) {
@@ -160,6 +167,7 @@ struct Operand {
     const void *ptr;
     int64_t ld;
     int kmajor;   // 1: contraction index contiguous
+    int embed;    // complex source read as its real 2 x 2 block embedding
 };
 
 hs_status launch_status(hipError_t e) { return e == hipSuccess ? HS_OK : HS_ERR_LAUNCH_FAILED; }
@@ -210,6 +218,7 @@ hs_status run_product(const Plan &P, const Operand &X, const Operand &Y, void *o
     pb.total_units = pack_units(P.gb, Y.kmajor);
     pb.vec = pack_vec_ok(P, Y);
     pb.exps = eb; pb.exp_tiles_k = P.tiles_k; pb.refine = P.f.form;
+    pb.embed = Y.embed;
     e = launch_pack(P.f.pack, Y.kmajor, pb, stream);
     if (e != hipSuccess) return HS_ERR_LAUNCH_FAILED;
 
@@ -323,7 +332,15 @@ size_t hs_workspace_size(hs_op op, int64_t m, int64_t n, int64_t k, hs_dtype dty
     const size_t bad = std::numeric_limits<size_t>::max();
     Plan P;
     switch (op) {
-        case HS_OP_GEMM:
+        case HS_OP_GEMM: {
+            hs_dtype base;
+            if (complex_base(dtype, &base)) {
+                if (m < 0 || n < 0 || k < 0 || make_plan(m, 2 * n, 2 * k, base, s, &P) != HS_OK) return bad;
+                return P.total;
+            }
+            if (make_plan(m, n, k, dtype, s, &P) != HS_OK) return bad;
+            return P.total;
+        }
         case HS_OP_GEMM_TN:
             if (make_plan(m, n, k, dtype, s, &P) != HS_OK) return bad;
             return P.total;
@@ -346,13 +363,26 @@ size_t hs_workspace_size(hs_op op, int64_t m, int64_t n, int64_t k, hs_dtype dty
 hs_status hs_gemm(int64_t m, int64_t n, int64_t k, hs_dtype dtype, hs_schedule s,
                   const void *A, int64_t lda, const void *B, int64_t ldb,
                   void *C, int64_t ldc, void *ws, size_t ws_bytes, void *stream) {
+    hs_dtype base;
+    if (complex_base(dtype, &base)) {
+        // one real product: A as m x 2k, B embedded as 2k x 2n, C as m x 2n
+        if (m < 0 || n < 0 || k < 0) return HS_ERR_INVALID_VALUE;
+        Plan P;
+        HS_TRY(make_plan(m, 2 * n, 2 * k, base, s, &P));
+        HS_TRY(check_mat(A, m, k, lda, 8));
+        HS_TRY(check_mat(B, k, n, ldb, 8));
+        HS_TRY(check_mat(C, m, n, ldc, 8));
+        HS_TRY(check_ws(P, ws, ws_bytes));
+        return run_product(P, Operand{A, 2 * lda, 1, 0}, Operand{B, 2 * ldb, 0, 1}, C, 2 * ldc, ws,
+                           (hipStream_t)stream);
+    }
     Plan P;
     HS_TRY(make_plan(m, n, k, dtype, s, &P));
     HS_TRY(check_mat(A, m, k, lda, P.f.in_esz));
     HS_TRY(check_mat(B, k, n, ldb, P.f.in_esz));
     HS_TRY(check_mat(C, m, n, ldc, P.f.out_f64 ? 8 : 4));
     HS_TRY(check_ws(P, ws, ws_bytes));
-    return run_product(P, Operand{A, lda, 1}, Operand{B, ldb, 0}, C, ldc, ws, (hipStream_t)stream);
+    return run_product(P, Operand{A, lda, 1, 0}, Operand{B, ldb, 0, 0}, C, ldc, ws, (hipStream_t)stream);
 }
 
 hs_status hs_gemm_tn(int64_t m, int64_t n, int64_t k, hs_dtype dtype, hs_schedule s,
@@ -364,7 +394,7 @@ hs_status hs_gemm_tn(int64_t m, int64_t n, int64_t k, hs_dtype dtype, hs_schedul
     HS_TRY(check_mat(B, k, n, ldb, P.f.in_esz));
     HS_TRY(check_mat(C, m, n, ldc, P.f.out_f64 ? 8 : 4));
     HS_TRY(check_ws(P, ws, ws_bytes));
-    return run_product(P, Operand{A, lda, 0}, Operand{B, ldb, 0}, C, ldc, ws, (hipStream_t)stream);
+    return run_product(P, Operand{A, lda, 0, 0}, Operand{B, ldb, 0, 0}, C, ldc, ws, (hipStream_t)stream);
 }
 
 hs_status hs_gemv(int64_t m, int64_t n, hs_dtype dtype, hs_schedule s,
@@ -426,8 +456,8 @@ hs_status hs_gemm_backward(int64_t m, int64_t n, int64_t k, hs_dtype dtype, hs_s
         HS_TRY(check_ws(Pb, ws, ws_bytes));
     }
     hipStream_t st = (hipStream_t)stream;
-    if (dA) HS_TRY(run_product(Pa, Operand{G, ldg, 1}, Operand{B, ldb, 1}, dA, ldda, ws, st));
-    if (dB) HS_TRY(run_product(Pb, Operand{A, lda, 0}, Operand{G, ldg, 0}, dB, lddb, ws, st));
+    if (dA) HS_TRY(run_product(Pa, Operand{G, ldg, 1, 0}, Operand{B, ldb, 1, 0}, dA, ldda, ws, st));
+    if (dB) HS_TRY(run_product(Pb, Operand{A, lda, 0, 0}, Operand{G, ldg, 0, 0}, dB, lddb, ws, st));
     return HS_OK;
 }
 

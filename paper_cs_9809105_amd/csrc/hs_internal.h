@@ -72,6 +72,10 @@ struct PackArgs {
     const int32_t *exps;     // fp8 only: tile exponents (Fp8ExpArgs)
     int64_t exp_tiles_k;
     int refine;              // fp8 only: write q1 as the second piece
+    int embed;               // MN-major source only: the source is a complex
+                             // matrix (interleaved re, im; ld in floats) and
+                             // the operand is its real 2 x 2 block embedding
+                             // [[re, im], [-im, re]] (2Kd x 2R)
 };
 
 struct MainArgs {

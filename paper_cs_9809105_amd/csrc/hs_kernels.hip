@@ -230,10 +230,21 @@ __global__ __launch_bounds__(256) void pack_kernel(PackArgs a) {
             const int64_t kin = kin0 + e;
             const int64_t kk = kk0 + e;
             const bool ok = rvalid && kin < g.S_k && kk < g.Kd;
-            const int64_t idx = KMAJOR ? row * a.ld + kk : kk * a.ld + row;
+            int64_t idx = KMAJOR ? row * a.ld + kk : kk * a.ld + row;
+            bool neg = false;
+            if constexpr (!KMAJOR && (KIND == PK_F32 || KIND == PK_SPLIT3)) {
+                if (a.embed) {
+                    // element (kk, row) of the embedding: complex b_tj with
+                    // t = kk / 2, j = row / 2; rows s = kk % 2 and columns
+                    // c = row % 2 of [[re, im], [-im, re]]
+                    const int64_t t = kk >> 1, sr = kk & 1, c = row & 1;
+                    idx = t * a.ld + (row - c) + (sr ^ c);
+                    neg = sr == 1 && c == 0;
+                }
+            }
             if constexpr (KIND == PK_F64) vals_d[e] = ok ? (double)src[idx] : 0.0;
             else if constexpr (KIND == PK_B16) vals_h[e] = ok ? (uint16_t)src[idx] : (uint16_t)0;
-            else vals_f[e] = ok ? (float)src[idx] : 0.0f;
+            else vals_f[e] = ok ? (neg ? -(float)src[idx] : (float)src[idx]) : 0.0f;
         }
     }
     // chunk = UPR planes of 16 bytes per row: [plane][row][16 bytes]

@@ -175,6 +175,12 @@ def _gemm(**kw):
     (dict(dt=B.HS_FP8_E4M3, m=64, n=64, k=96, lda=96, ldb=64, ldc=64, p=2), B.HS_ERR_NOT_SUPPORTED),
     (dict(dt=B.HS_FP8_E4M3_R1, m=48, n=64, k=128, lda=128, ldb=64, ldc=64, p=2), B.HS_ERR_NOT_SUPPORTED),
     (dict(dt=B.HS_FP8_E4M3_R1, m=256, n=64, k=768, lda=768, ldb=64, ldc=64, p=4, K=3), B.HS_ERR_INVALID_VALUE),
+    # complex: 8-byte elements, ld in complex elements, workspace of the 2k x 2n embedding
+    (dict(dt=B.HS_C32, A=FAKE + 4), B.HS_ERR_INVALID_VALUE),
+    (dict(dt=B.HS_C32_SPLIT3_BF16, C=FAKE + 4), B.HS_ERR_INVALID_VALUE),
+    (dict(dt=B.HS_C32, ldb=7), B.HS_ERR_INVALID_VALUE),
+    (dict(dt=B.HS_C32, wsb=16), B.HS_ERR_WORKSPACE_TOO_SMALL),
+    (dict(dt=B.HS_C32, k=-1), B.HS_ERR_INVALID_VALUE),
 ])
 def test_gemm_rejects(kw, code):
     assert _gemm(**kw) == code
@@ -226,3 +232,23 @@ def test_empty_problems_need_nothing():
 
 def test_profile_end_without_begin():
     assert B.lib().hs_profile_end(None, None) == B.HS_ERR_INVALID_VALUE
+
+
+def test_complex_forms_are_product_only():
+    L = B.lib()
+    s = B.hs_schedule(2, 0)
+    for dt in (B.HS_C32, B.HS_C32_SPLIT3_BF16):
+        assert L.hs_gemm_tn(8, 8, 8, dt, s, FAKE, 8, FAKE, 8, FAKE, 8, FAKE, 1 << 30, None) == B.HS_ERR_NOT_SUPPORTED
+        assert L.hs_gemv(8, 8, dt, s, FAKE, 8, FAKE, FAKE, None, 0, None) == B.HS_ERR_NOT_SUPPORTED
+        assert L.hs_gemm_backward(8, 8, 8, dt, s, FAKE, 8, FAKE, 8, FAKE, 8, FAKE, 8, FAKE, 8, FAKE, 1 << 30,
+                                  None) == B.HS_ERR_NOT_SUPPORTED
+        for op in (B.HS_OP_GEMM_TN, B.HS_OP_GEMV, B.HS_OP_BACKWARD):
+            assert B.hs_workspace_size(op, 64, 64, 64, dt, 4) == B.SIZE_MAX
+
+
+def test_complex_workspace_is_that_of_the_real_embedding():
+    ws = B.hs_workspace_size
+    for (m, n, k, p, K) in [(64, 48, 80, 4, 2), (300, 200, 100, 8, 0), (128, 128, 128, 16, 4)]:
+        assert ws(B.HS_OP_GEMM, m, n, k, "c32", p, K) == ws(B.HS_OP_GEMM, m, 2 * n, 2 * k, "f32", p, K)
+        assert ws(B.HS_OP_GEMM, m, n, k, "c32_split3_bf16", p, K) == \
+            ws(B.HS_OP_GEMM, m, 2 * n, 2 * k, "split3_bf16", p, K)

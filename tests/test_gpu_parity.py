@@ -455,3 +455,76 @@ def test_fp8_quantisation_bit_exact_backward(dt):
     ref = P.fp8_dequantized(Gf, dt == "fp8_e4m3_r1")
     assert np.array_equal(host(dA), ref)
     assert np.array_equal(host(dB), ref)
+
+
+# ---------------------------------------------------------------------------
+# Complex data (the complex workload of Sec. 7): hs_gemm on complex64, run as
+# one real product of A (m x 2k) and the 2 x 2 block embedding of B.
+# ---------------------------------------------------------------------------
+CPLX = ["c32", "c32_split3_bf16"]
+CPLX_CASES = [(64, 48, 80, 4, 2), (77, 45, 333, 5, 1), (256, 200, 320, 8, 0), (512, 384, 640, 16, 4),
+              (130, 260, 90, 3, 3), (1, 1, 1, 1, 1)]
+
+
+def _cplx_dev(shape, seed, gen=inputs.normal):
+    x = gen(shape, seed) + 1j * gen(shape, seed + 1)
+    t = torch.from_numpy(np.ascontiguousarray(x.astype(np.complex64)))
+    return t.cuda(), t.numpy().astype(np.complex128)
+
+
+@pytest.mark.parametrize("dt", CPLX)
+@pytest.mark.parametrize("case", CPLX_CASES)
+def test_complex_product(dt, case):
+    _skip_no_gpu()
+    m, n, k, p, K = case
+    A, Ah = _cplx_dev((m, k), 950 + m)
+    B, Bh = _cplx_dev((k, n), 960 + n)
+    out = poisoned((m, n), torch.complex64)
+    note("complex", dt, case)
+    C = hs.hs_gemm(A, B, dtype=dt, p=p, K=K, out=out)
+    torch.cuda.synchronize()
+    got = C.cpu().numpy().astype(np.complex128)
+    assert not np.isnan(got).any()
+    e = err_row(got, oracle.complex_gemm(Ah, Bh))
+    assert e <= 1e-5, (dt, case, e)
+
+
+@pytest.mark.parametrize("dt", CPLX)
+def test_complex_gaussian_integers_bit_exact(dt):
+    _skip_no_gpu()
+    m, n, k = 200, 136, 264
+    A, Ah = _cplx_dev((m, k), 970, inputs.small_int)
+    B, Bh = _cplx_dev((k, n), 972, inputs.small_int)
+    note("complex small int", dt)
+    C = hs.hs_gemm(A, B, dtype=dt, p=8, K=2)
+    torch.cuda.synchronize()
+    assert np.array_equal(C.cpu().numpy().astype(np.complex128), oracle.complex_gemm(Ah, Bh))
+
+
+def test_complex_strided_views():
+    _skip_no_gpu()
+    Abig, Ahb = _cplx_dev((100, 150), 980)
+    Bbig, Bhb = _cplx_dev((130, 90), 982)
+    A, B = Abig[:, 10:130], Bbig[5:125, :70]        # row strides 150 and 90 complex elements
+    note("complex views")
+    C = hs.hs_gemm(A, B, dtype="c32_split3_bf16", p=6, K=2)
+    torch.cuda.synchronize()
+    ref = oracle.complex_gemm(Ahb[:, 10:130], Bhb[5:125, :70])
+    assert err_row(C.cpu().numpy().astype(np.complex128), ref) <= 1e-5
+
+
+def test_complex_4096_sampled_rows():
+    """n = 4096 complex, p = 64, both forms, on 32 sampled rows."""
+    _skip_no_gpu()
+    n = 4096
+    A, Ah = _cplx_dev((n, n), 990)
+    B, Bh = _cplx_dev((n, n), 992)
+    rows = inputs.sample_rows(n, 32, seed=994)
+    ref = oracle.complex_gemm_rows(Ah, Bh, rows)
+    for dt in CPLX:
+        note("complex 4096", dt)
+        C = hs.hs_gemm(A, B, dtype=dt, p=64, K=8)
+        torch.cuda.synchronize()
+        e = err_row(C.cpu().numpy().astype(np.complex128)[rows], ref)
+        print("complex n=4096 %s err_row %.3e" % (dt, e))
+        assert e <= 1e-5
