@@ -107,9 +107,21 @@ def cpu_baseline(A64, B64, G64, target_s):
     oracle.grad_b_rows(A64, G64, rows_k)
     dt = time.perf_counter() - t0
     flops = 2.0 * nrows * (n * k + n * k + m * n)
+    # the same oracle on one thread, over a smaller sample (one row per core)
+    oracle.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        oracle.gemm_rows(A64, B64, rows_m[:cal])
+        oracle.grad_a_rows(G64, B64, rows_m[:cal])
+        oracle.grad_b_rows(A64, G64, rows_k[:cal])
+        dt1 = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(cores)
+    flops1 = 2.0 * cal * (n * k + n * k + m * n)
     return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
-            "sample": "%d sampled rows of each of C, dA, dB (M=%d Kd=%d N=%d, FP64 triple loop, %.1f s)"
-                      % (nrows, m, k, n, dt)}
+            "value_1thread": flops1 / dt1 / 1e12,
+            "sample": "%d sampled rows of each of C, dA, dB (M=%d Kd=%d N=%d, FP64 triple loop, %.1f s); "
+                      "1-thread figure on %d rows (%.1f s)" % (nrows, m, k, n, dt, cal, dt1)}
 
 
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "mm_kernel_split3_f32_n8192_traffic.json")

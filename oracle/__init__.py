@@ -42,12 +42,19 @@ def _load():
         lib.hs_oracle_gemm_rows.argtypes = [i64, i64, dp, i64, dp, i64, ip, i64, dp, i64]
         lib.hs_oracle_gemm_tn_rows.argtypes = [i64, i64, dp, i64, dp, i64, ip, i64, dp, i64]
         lib.hs_oracle_grad_a_rows.argtypes = [i64, i64, dp, i64, dp, i64, ip, i64, dp, i64]
+        lib.hs_oracle_set_threads.argtypes = [ctypes.c_int]
+        lib.hs_oracle_set_threads.restype = None
         for f in ("hs_oracle_gemm", "hs_oracle_gemm_tn", "hs_oracle_gemv",
                   "hs_oracle_backward", "hs_oracle_gemm_rows", "hs_oracle_gemm_tn_rows",
                   "hs_oracle_grad_a_rows"):
             getattr(lib, f).restype = None
         _lib = lib
     return _lib
+
+
+def set_threads(n):
+    """Threads of the oracle's loops (n <= 0: all); for timing only."""
+    _load().hs_oracle_set_threads(int(n))
 
 
 def _d(x):

@@ -26,6 +26,14 @@
  */
 #include <stdint.h>
 #include <stddef.h>
+#include <omp.h>
+
+/* Threads used by the loops below (n <= 0: the OpenMP default).  Only for
+ * timing the oracle; the results do not depend on it. */
+void hs_oracle_set_threads(int n)
+{
+    omp_set_num_threads(n > 0 ? n : omp_get_num_procs());
+}
 
 /* C[m,n] = A[m,k] . B[k,n]  (Eq. PRODUCT, with A n x m and B m x n
  * generalised to rectangular M x Kd times Kd x N). */

@@ -283,3 +283,15 @@ def test_planted_mistake_is_caught(name):
 def test_unmutated_oracle_passes_all_pins():
     res = all_pins(oracle.gemm, oracle.gemm_tn, oracle.gemv, oracle.backward)
     assert all(res.values()), res
+
+
+def test_thread_count_does_not_change_results():
+    A = inputs.normal((67, 45), seed=71)
+    B = inputs.normal((45, 38), seed=72)
+    ref = oracle.gemm(A, B)
+    oracle.set_threads(1)
+    try:
+        one = oracle.gemm(A, B)
+    finally:
+        oracle.set_threads(0)
+    assert np.array_equal(one, ref)
