@@ -78,16 +78,17 @@ extern "C" {
  *                  with q1 = e4m3((a s - q0) s1), s1 a power of two per tile;
  *                  products q0 q0', q0 q1', q1 q0'.
  *  HS_C32          in complex64, out complex64 (interleaved re, im FP32
- *                  pairs; ld* in complex elements).  hs_gemm only.  The
+ *                  pairs; ld* in complex elements).  The
  *                  complex product (the complex-data workload of Sec. 7) as
  *                  one real product on FP32 MFMA: A read as an m x 2k real
  *                  matrix, B embedded as the 2k x 2n real matrix whose
  *                  2 x 2 block (t, j) is [[re, im], [-im, re]] of b_tj, C
  *                  written as m x 2n = interleaved complex.  4 real
  *                  multiplications per complex one (no 3M rewrite: it
- *                  cancels).
+ *                  cancels).  Also hs_gemm_backward (dA = G B^H, dB = A^H G).
  *  HS_C32_SPLIT3_BF16  the same with the split-BF16 arithmetic of
- *                  HS_SPLIT3_BF16 (FP32-accurate).  hs_gemm only. */
+ *                  HS_SPLIT3_BF16 (FP32-accurate).  hs_gemm and
+ *                  hs_gemm_backward. */
 typedef enum {
     HS_F64 = 0,
     HS_F32 = 1,
@@ -179,7 +180,9 @@ hs_status hs_gemv(int64_t m, int64_t n, hs_dtype dtype, hs_schedule s,
  * dA: m x k (ldda >= k), dB: k x n (lddb >= n).  Either output may be NULL
  * to skip it.  Both products follow the same schedule `s`, run one after
  * the other on `stream` and may share the workspace.  Storage types as for
- * hs_gemm (G has the input type). */
+ * hs_gemm (G has the input type).  For the complex dtypes the gradients are
+ * dA = G . B^H and dB = A^H . G (conjugate transposes; G = dL/dC in the
+ * convention where a real loss L has gradient dL/dre + i dL/dim). */
 hs_status hs_gemm_backward(int64_t m, int64_t n, int64_t k, hs_dtype dtype, hs_schedule s,
                            const void *A, int64_t lda, const void *B, int64_t ldb,
                            const void *G, int64_t ldg,

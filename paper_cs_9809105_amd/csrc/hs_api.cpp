@@ -176,7 +176,7 @@ hs_status launch_status(hipError_t e) { return e == hipSuccess ? HS_OK : HS_ERR_
 // elements are contiguous, aligned and either all inside or all outside
 // the matrix and its contraction block.
 int pack_vec_ok(const Plan &P, const Operand &X) {
-    if (!X.kmajor) return 0;
+    if (!X.kmajor || X.embed != EMB_NONE) return 0;
     const int64_t ue = 16 / P.f.packed_esz;          // source elements per unit
     const int64_t in = P.f.in_esz;
     if (P.f.pack == PK_SPLIT3) {                     // 8 fp32 per unit (two loads)
@@ -211,6 +211,7 @@ hs_status run_product(const Plan &P, const Operand &X, const Operand &Y, void *o
     pa.total_units = pack_units(P.ga, X.kmajor);
     pa.vec = pack_vec_ok(P, X);
     pa.exps = ea; pa.exp_tiles_k = P.tiles_k; pa.refine = P.f.form;
+    pa.embed = X.embed;
     hipError_t e = launch_pack(P.f.pack, X.kmajor, pa, stream);
     if (e != hipSuccess) return HS_ERR_LAUNCH_FAILED;
     PackArgs pb{};
@@ -352,6 +353,13 @@ size_t hs_workspace_size(hs_op op, int64_t m, int64_t n, int64_t k, hs_dtype dty
         }
         case HS_OP_BACKWARD: {
             Plan Pa, Pb;
+            hs_dtype base;
+            if (complex_base(dtype, &base)) {
+                if (m < 0 || n < 0 || k < 0) return bad;
+                if (make_plan(m, 2 * k, 2 * n, base, s, &Pa) != HS_OK) return bad;
+                if (make_plan(k, 2 * n, 2 * m, base, s, &Pb) != HS_OK) return bad;
+                return std::max(Pa.total, Pb.total);
+            }
             if (make_plan(m, k, n, dtype, s, &Pa) != HS_OK) return bad;
             if (make_plan(k, n, m, dtype, s, &Pb) != HS_OK) return bad;
             return std::max(Pa.total, Pb.total);
@@ -373,7 +381,7 @@ hs_status hs_gemm(int64_t m, int64_t n, int64_t k, hs_dtype dtype, hs_schedule s
         HS_TRY(check_mat(B, k, n, ldb, 8));
         HS_TRY(check_mat(C, m, n, ldc, 8));
         HS_TRY(check_ws(P, ws, ws_bytes));
-        return run_product(P, Operand{A, 2 * lda, 1, 0}, Operand{B, 2 * ldb, 0, 1}, C, 2 * ldc, ws,
+        return run_product(P, Operand{A, 2 * lda, 1, EMB_NONE}, Operand{B, 2 * ldb, 0, EMB_BLOCKS}, C, 2 * ldc, ws,
                            (hipStream_t)stream);
     }
     Plan P;
@@ -382,7 +390,7 @@ hs_status hs_gemm(int64_t m, int64_t n, int64_t k, hs_dtype dtype, hs_schedule s
     HS_TRY(check_mat(B, k, n, ldb, P.f.in_esz));
     HS_TRY(check_mat(C, m, n, ldc, P.f.out_f64 ? 8 : 4));
     HS_TRY(check_ws(P, ws, ws_bytes));
-    return run_product(P, Operand{A, lda, 1, 0}, Operand{B, ldb, 0, 0}, C, ldc, ws, (hipStream_t)stream);
+    return run_product(P, Operand{A, lda, 1, EMB_NONE}, Operand{B, ldb, 0, EMB_NONE}, C, ldc, ws, (hipStream_t)stream);
 }
 
 hs_status hs_gemm_tn(int64_t m, int64_t n, int64_t k, hs_dtype dtype, hs_schedule s,
@@ -394,7 +402,7 @@ hs_status hs_gemm_tn(int64_t m, int64_t n, int64_t k, hs_dtype dtype, hs_schedul
     HS_TRY(check_mat(B, k, n, ldb, P.f.in_esz));
     HS_TRY(check_mat(C, m, n, ldc, P.f.out_f64 ? 8 : 4));
     HS_TRY(check_ws(P, ws, ws_bytes));
-    return run_product(P, Operand{A, lda, 0, 0}, Operand{B, ldb, 0, 0}, C, ldc, ws, (hipStream_t)stream);
+    return run_product(P, Operand{A, lda, 0, EMB_NONE}, Operand{B, ldb, 0, EMB_NONE}, C, ldc, ws, (hipStream_t)stream);
 }
 
 hs_status hs_gemv(int64_t m, int64_t n, hs_dtype dtype, hs_schedule s,
@@ -440,6 +448,33 @@ hs_status hs_gemm_backward(int64_t m, int64_t n, int64_t k, hs_dtype dtype, hs_s
                            const void *G, int64_t ldg,
                            void *dA, int64_t ldda, void *dB, int64_t lddb,
                            void *ws, size_t ws_bytes, void *stream) {
+    hs_dtype base;
+    if (complex_base(dtype, &base)) {
+        // dA = G . B^H: G as m x 2n reals, B^H as the 2n x 2k block embedding
+        // of conj(B)^T; dB = A^H . G: conj(A)^T as k x 2m reals, G as the
+        // 2m x 2n block embedding.  Outputs as interleaved complex.
+        if (m < 0 || n < 0 || k < 0) return HS_ERR_INVALID_VALUE;
+        Plan Pa, Pb;
+        HS_TRY(make_plan(m, 2 * k, 2 * n, base, s, &Pa));
+        HS_TRY(make_plan(k, 2 * n, 2 * m, base, s, &Pb));
+        HS_TRY(check_mat(G, m, n, ldg, 8));
+        if (dA) {
+            HS_TRY(check_mat(B, k, n, ldb, 8));
+            HS_TRY(check_mat(dA, m, k, ldda, 8));
+            HS_TRY(check_ws(Pa, ws, ws_bytes));
+        }
+        if (dB) {
+            HS_TRY(check_mat(A, m, k, lda, 8));
+            HS_TRY(check_mat(dB, k, n, lddb, 8));
+            HS_TRY(check_ws(Pb, ws, ws_bytes));
+        }
+        hipStream_t st = (hipStream_t)stream;
+        if (dA) HS_TRY(run_product(Pa, Operand{G, 2 * ldg, 1, EMB_NONE}, Operand{B, 2 * ldb, 1, EMB_BLOCKS_H},
+                                   dA, 2 * ldda, ws, st));
+        if (dB) HS_TRY(run_product(Pb, Operand{A, 2 * lda, 0, EMB_CONJ}, Operand{G, 2 * ldg, 0, EMB_BLOCKS},
+                                   dB, 2 * lddb, ws, st));
+        return HS_OK;
+    }
     Plan Pa, Pb;
     HS_TRY(make_plan(m, k, n, dtype, s, &Pa));   // dA[m,k] = G[m,n] . B[k,n]^T
     HS_TRY(make_plan(k, n, m, dtype, s, &Pb));   // dB[k,n] = A[m,k]^T . G[m,n]
@@ -456,8 +491,8 @@ hs_status hs_gemm_backward(int64_t m, int64_t n, int64_t k, hs_dtype dtype, hs_s
         HS_TRY(check_ws(Pb, ws, ws_bytes));
     }
     hipStream_t st = (hipStream_t)stream;
-    if (dA) HS_TRY(run_product(Pa, Operand{G, ldg, 1, 0}, Operand{B, ldb, 1, 0}, dA, ldda, ws, st));
-    if (dB) HS_TRY(run_product(Pb, Operand{A, lda, 0, 0}, Operand{G, ldg, 0, 0}, dB, lddb, ws, st));
+    if (dA) HS_TRY(run_product(Pa, Operand{G, ldg, 1, EMB_NONE}, Operand{B, ldb, 1, EMB_NONE}, dA, ldda, ws, st));
+    if (dB) HS_TRY(run_product(Pb, Operand{A, lda, 0, EMB_NONE}, Operand{G, ldg, 0, EMB_NONE}, dB, lddb, ws, st));
     return HS_OK;
 }
 

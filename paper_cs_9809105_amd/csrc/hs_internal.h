@@ -72,10 +72,20 @@ struct PackArgs {
     const int32_t *exps;     // fp8 only: tile exponents (Fp8ExpArgs)
     int64_t exp_tiles_k;
     int refine;              // fp8 only: write q1 as the second piece
-    int embed;               // MN-major source only: the source is a complex
-                             // matrix (interleaved re, im; ld in floats) and
-                             // the operand is its real 2 x 2 block embedding
-                             // [[re, im], [-im, re]] (2Kd x 2R)
+    int embed;               // complex sources (interleaved re, im; ld in
+                             // floats), see PackEmbed
+};
+
+// How the pack kernel reads a complex source (element (kk, row) of the real
+// operand; kk the contraction index, row the output row or column).
+enum PackEmbed {
+    EMB_NONE = 0,      // real source, or complex already laid out as reals
+    EMB_BLOCKS = 1,    // MN-major source X[t][j] (t = kk/2, j = row/2): the real
+                       // 2 x 2 block embedding [[re x, im x], [-im x, re x]]
+    EMB_BLOCKS_H = 2,  // K-major source X[t][j] (t = row/2, j = kk/2): the block
+                       // embedding of conj(X[t][j]), i.e. of X^H
+    EMB_CONJ = 3       // MN-major source X[i][t] (i = kk/2, t = row): conj(X)^T
+                       // as reals, kk = 2i + (0 re, 1 im)
 };
 
 struct MainArgs {

@@ -232,14 +232,20 @@ __global__ __launch_bounds__(256) void pack_kernel(PackArgs a) {
             const bool ok = rvalid && kin < g.S_k && kk < g.Kd;
             int64_t idx = KMAJOR ? row * a.ld + kk : kk * a.ld + row;
             bool neg = false;
-            if constexpr (!KMAJOR && (KIND == PK_F32 || KIND == PK_SPLIT3)) {
-                if (a.embed) {
-                    // element (kk, row) of the embedding: complex b_tj with
-                    // t = kk / 2, j = row / 2; rows s = kk % 2 and columns
-                    // c = row % 2 of [[re, im], [-im, re]]
-                    const int64_t t = kk >> 1, sr = kk & 1, c = row & 1;
-                    idx = t * a.ld + (row - c) + (sr ^ c);
+            if constexpr (KIND == PK_F32 || KIND == PK_SPLIT3) {
+                // complex sources: sr = kk % 2 and c = row % 2 pick the entry
+                // of the 2 x 2 block [[re, im], [-im, re]]
+                const int64_t sr = kk & 1, c = row & 1;
+                if (!KMAJOR && a.embed == EMB_BLOCKS) {
+                    idx = (kk >> 1) * a.ld + (row - c) + (sr ^ c);
                     neg = sr == 1 && c == 0;
+                } else if (KMAJOR && a.embed == EMB_BLOCKS_H) {
+                    // conj(x): the im entries change sign
+                    idx = (row >> 1) * a.ld + 2 * (kk >> 1) + (sr ^ c);
+                    neg = sr == 0 && c == 1;
+                } else if (!KMAJOR && a.embed == EMB_CONJ) {
+                    idx = (kk >> 1) * a.ld + 2 * row + sr;
+                    neg = sr == 1;
                 }
             }
             if constexpr (KIND == PK_F64) vals_d[e] = ok ? (double)src[idx] : 0.0;

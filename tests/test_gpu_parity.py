@@ -528,3 +528,55 @@ def test_complex_4096_sampled_rows():
         e = err_row(C.cpu().numpy().astype(np.complex128)[rows], ref)
         print("complex n=4096 %s err_row %.3e" % (dt, e))
         assert e <= 1e-5
+
+
+CPLX_BW_CASES = [(64, 48, 80, 4, 2), (77, 45, 133, 5, 1), (256, 200, 320, 8, 0), (130, 260, 90, 3, 3)]
+
+
+@pytest.mark.parametrize("dt", CPLX)
+@pytest.mark.parametrize("case", CPLX_BW_CASES)
+def test_complex_backward(dt, case):
+    """dA = G . B^H and dB = A^H . G (PyTorch's convention for complex
+    gradients) against the oracle."""
+    _skip_no_gpu()
+    m, n, k, p, K = case
+    A, Ah = _cplx_dev((m, k), 1000 + m)
+    B, Bh = _cplx_dev((k, n), 1010 + n)
+    G, Gh = _cplx_dev((m, n), 1020 + k)
+    note("complex backward", dt, case)
+    dA, dB = hs.hs_gemm_backward(A, B, G, dtype=dt, p=p, K=K)
+    torch.cuda.synchronize()
+    eA = err_row(dA.cpu().numpy().astype(np.complex128), oracle.complex_gemm(Gh, np.conj(Bh).T))
+    eB = err_row(dB.cpu().numpy().astype(np.complex128), oracle.complex_gemm(np.conj(Ah).T, Gh))
+    assert max(eA, eB) <= 1e-5, (dt, case, eA, eB)
+
+
+@pytest.mark.parametrize("dt", CPLX)
+def test_complex_backward_gaussian_integers_bit_exact(dt):
+    _skip_no_gpu()
+    m, n, k = 136, 200, 72
+    A, Ah = _cplx_dev((m, k), 1030, inputs.small_int)
+    B, Bh = _cplx_dev((k, n), 1032, inputs.small_int)
+    G, Gh = _cplx_dev((m, n), 1034, inputs.small_int)
+    note("complex backward small int", dt)
+    dA, dB = hs.hs_gemm_backward(A, B, G, dtype=dt, p=8, K=2)
+    torch.cuda.synchronize()
+    assert np.array_equal(dA.cpu().numpy().astype(np.complex128), oracle.complex_gemm(Gh, np.conj(Bh).T))
+    assert np.array_equal(dB.cpu().numpy().astype(np.complex128), oracle.complex_gemm(np.conj(Ah).T, Gh))
+
+
+def test_complex_autograd():
+    _skip_no_gpu()
+    m, k, n = 96, 64, 80
+    A, Ah = _cplx_dev((m, k), 1040)
+    B, Bh = _cplx_dev((k, n), 1042)
+    G, Gh = _cplx_dev((m, n), 1044)
+    A.requires_grad_(True)
+    B.requires_grad_(True)
+    note("complex autograd")
+    C = hs_autograd.matmul(A, B, dtype="c32_split3_bf16", p=4, K=2)
+    C.backward(G)
+    torch.cuda.synchronize()
+    assert err_row(C.detach().cpu().numpy().astype(np.complex128), oracle.complex_gemm(Ah, Bh)) <= 1e-5
+    assert err_row(A.grad.cpu().numpy().astype(np.complex128), oracle.complex_gemm(Gh, np.conj(Bh).T)) <= 1e-5
+    assert err_row(B.grad.cpu().numpy().astype(np.complex128), oracle.complex_gemm(np.conj(Ah).T, Gh)) <= 1e-5

@@ -68,3 +68,42 @@ def test_error_metric_counts_imaginary_parts():
     ref = np.array([[1 + 1j, 2 - 1j]])
     assert err_row(ref, ref) == 0.0
     assert err_row(ref + 1e-3j, ref) > 1e-4        # an error only in the imaginary parts
+
+
+def _blocks(X):
+    """Real 2 x 2 block embedding of X (r x c complex): 2r x 2c reals with
+    block (t, j) = [[re x, im x], [-im x, re x]]."""
+    r, c = X.shape
+    E = np.zeros((2 * r, 2 * c))
+    E[0::2, 0::2], E[0::2, 1::2] = X.real, X.imag
+    E[1::2, 0::2], E[1::2, 1::2] = -X.imag, X.real
+    return E
+
+
+def _as_reals(X):
+    R = np.empty((X.shape[0], 2 * X.shape[1]))
+    R[:, 0::2], R[:, 1::2] = X.real, X.imag
+    return R
+
+
+def test_backward_embeddings():
+    """The gradients of C = A . B for complex data (G = dL/dC in PyTorch's
+    convention): dA = G . B^H and dB = A^H . G, each as one real product of
+    (complex as reals) and (block embedding), as the library runs them."""
+    import torch
+    A = _cplx((6, 5), 23, inputs.small_int)
+    B = _cplx((5, 4), 25, inputs.small_int)
+    G = _cplx((6, 4), 27, inputs.small_int)
+    # PyTorch's own complex autograd fixes the convention
+    At = torch.tensor(A, requires_grad=True)
+    Bt = torch.tensor(B, requires_grad=True)
+    (At @ Bt).backward(torch.tensor(G))
+    dA = oracle.complex_gemm(G, np.conj(B).T)
+    dB = oracle.complex_gemm(np.conj(A).T, G)
+    assert np.array_equal(At.grad.numpy(), dA) and np.array_equal(Bt.grad.numpy(), dB)
+    # dA: G as reals times the block embedding of B^H
+    dA_r = oracle.gemm(_as_reals(G), _blocks(np.conj(B).T))
+    assert np.array_equal(dA_r, _as_reals(dA))
+    # dB: conj(A)^T as reals times the block embedding of G
+    dB_r = oracle.gemm(_as_reals(np.conj(A).T), _blocks(G))
+    assert np.array_equal(dB_r, _as_reals(dB))
