@@ -167,7 +167,7 @@ struct Operand {
     const void *ptr;
     int64_t ld;
     int kmajor;   // 1: contraction index contiguous
-    int embed;    // complex source read as its real 2 x 2 block embedding
+    int embed;    // how a complex source is read (PackEmbed)
 };
 
 hs_status launch_status(hipError_t e) { return e == hipSuccess ? HS_OK : HS_ERR_LAUNCH_FAILED; }
