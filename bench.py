@@ -238,16 +238,16 @@ def complex_main(args):
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         ms, launches = hs.hs_profile_end()
-        return wall, ms / max(launches, 1)
+        return wall, ms / max(launches, 1), launches
 
     useful = 3 * 8.0 * n ** 3                      # per step
-    wall, avg = timed(form, args.steps, args.warmup)
-    mfma = (6 if form == "c32_split3_bf16" else 1) * 8.0 * n ** 3   # per main-kernel launch
+    wall, avg, launches_c = timed(form, args.steps, args.warmup)
+    mfma = (6 if form == "c32_split3_bf16" else 1) * 8.0 * n ** 3 * 3 * args.steps   # all timed launches
     peak = PEAK["bf16" if form == "c32_split3_bf16" else "f32"]
-    achieved = mfma / (avg * 1e-3) / 1e12
+    achieved = mfma / (avg * launches_c * 1e-3) / 1e12
     comparison = None
     if args.compare and form != "c32":
-        w2, a2 = timed("c32", max(2, args.steps // 2), 1)
+        w2, a2, _ = timed("c32", max(2, args.steps // 2), 1)
         comparison = {"c32": {"value": useful * max(2, args.steps // 2) / w2 / 1e12, "avg_main_kernel_ms": a2}}
     cpu = None
     if args.cpu_seconds > 0:
@@ -275,7 +275,7 @@ def complex_main(args):
                    "M": n, "Kd": n, "N": n, "p": p, "K": K, "form": form},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": None, "kernel": "mm_kernel (main MFMA loop)",
-                     "avg_kernel_ms": avg, "launches": 3 * args.steps},
+                     "avg_kernel_ms": avg, "launches": launches_c},
         "comparison": comparison, "cpu_baseline": cpu}))
 
 
@@ -323,9 +323,10 @@ def main():
     ms_step = wall * 1e3 / args.steps
     value = useful * args.steps / wall / 1e12
     avg_kernel_ms = kern_ms / max(launches, 1)
-    mfma_flops = MFMA_PRODUCTS[args.form] * 2.0 * m * kd * n  # per main-kernel launch (all three
-    # products of a step have the same flop count)
-    achieved = mfma_flops / (avg_kernel_ms * 1e-3) / 1e12
+    # MFMA work of all timed main-kernel launches (three products per step,
+    # each 2 m kd n times the form's MFMA products) over their summed time
+    mfma_flops = MFMA_PRODUCTS[args.form] * 2.0 * m * kd * n * 3 * args.steps
+    achieved = mfma_flops / (kern_ms * 1e-3) / 1e12
     peak = PEAK[MFMA_PEAK_KEY[args.form]]
 
     comparison = None

@@ -32,6 +32,13 @@ using namespace hs;
 namespace {
 
 const int kMaxP = 4096;
+// Bytes of partial planes per column phase (0: all columns in one phase).
+// 128 MB costs no measurable time at n = 8192 (two to four phases) and bounds
+// the partial workspace whatever K and N.
+#ifndef HS_PARTIAL_BUDGET
+#define HS_PARTIAL_BUDGET (128ull << 20)
+#endif
+const size_t kPartialBudget = (size_t)HS_PARTIAL_BUDGET;
 const size_t kAlign = 256;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -76,6 +83,7 @@ struct Plan {
     int64_t M, N, Kd;
     OperandGeom ga, gb;
     size_t off_a, off_b, off_w, total;
+    int64_t phase_tiles;              // column tiles per phase of the partial planes
     size_t off_ea, off_eb;            // fp8: tile exponents of each operand
     int64_t tiles_k, tiles_ra, tiles_rb;
 };
@@ -142,7 +150,18 @@ hs_status make_plan(int64_t M, int64_t N, int64_t Kd, hs_dtype dt, hs_schedule s
     P->off_a = off; off = align_up(off + (size_t)(a.piece_bytes * NP));
     P->off_b = off; off = align_up(off + (size_t)(b.piece_bytes * NP));
     P->off_w = off;
-    if (P->K > 1) off = align_up(off + (size_t)P->K * M * N * (P->f.out_f64 ? 8 : 4));
+    // Partial planes (Sec. 6.2, cyclic mapping): the columns of C are
+    // processed in phases of phase_tiles tiles, and the K partial planes hold
+    // one phase, so their size is bounded by kPartialBudget (at least one
+    // tile wide) instead of growing as K M N.
+    P->phase_tiles = b.GS;
+    if (P->K > 1) {
+        const size_t esz = P->f.out_f64 ? 8 : 4;
+        const size_t per_tile = (size_t)P->K * M * BNT * esz;
+        if (kPartialBudget > 0 && per_tile > 0)
+            P->phase_tiles = std::max<int64_t>(1, std::min<int64_t>(b.GS, (int64_t)(kPartialBudget / per_tile)));
+        off = align_up(off + (size_t)P->K * M * std::min<int64_t>(N, P->phase_tiles * BNT) * esz);
+    }
     P->tiles_k = ceil_div(Kd, FP8_TILE);
     P->tiles_ra = ceil_div(M, FP8_TILE);
     P->tiles_rb = ceil_div(N, FP8_TILE);
@@ -228,40 +247,57 @@ hs_status run_product(const Plan &P, const Operand &X, const Operand &Y, void *o
     m.B = w + P.off_b; m.b_piece = P.gb.piece_bytes;
     m.a_bytes = P.ga.piece_bytes * P.ga.pieces;
     m.b_bytes = P.gb.piece_bytes * P.gb.pieces;
-    const bool partials = P.K > 1;
-    m.out = partials ? (void *)(w + P.off_w) : out;
-    m.ldo = partials ? P.N : ldo;
-    m.plane = P.M * P.N;
     m.p = P.p; m.K = P.K; m.Kt = P.Kt;
     m.MS = P.ga.grp_rows; m.GS = P.ga.GS; m.nch = P.ga.nch; m.S_r = P.ga.S_r;
-    m.M = P.M; m.N = P.N; m.n_ntiles = P.gb.GS; m.out_f64 = f64;
-    {   // 32 workgroups per XCD: grp_v class members x grp_t column tiles
-        int64_t gt = 1;
-        while (gt * 2 <= 8 && gt * 2 <= P.gb.GS) gt *= 2;
-        const int64_t members = (int64_t)P.Kt * P.ga.GS;
-        int64_t gv = 32 / gt;
-        while (gv > 1 && gv / 2 >= members) gv /= 2;
-        m.grp_t = gt; m.grp_v = gv;
-        m.n_tg = ceil_div(P.gb.GS, gt);
-        m.n_ug = ceil_div(members, gv);
-    }
+    m.M = P.M; m.N = P.N; m.out_f64 = f64;
     m.a_exps = ea; m.b_exps = eb; m.a_tiles_k = P.tiles_k; m.b_tiles_k = P.tiles_k;
     m.S_k = P.ga.S_k; m.Kd = P.Kd;
-
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    if (g_prof) {
-        if (hipEventCreate(&ev0) != hipSuccess || hipEventCreate(&ev1) != hipSuccess)
-            return HS_ERR_LAUNCH_FAILED;
-        (void)hipEventRecord(ev0, stream);
+    const bool partials = P.K > 1;
+    const int64_t BNT = P.gb.grp_rows;
+    for (int64_t t0 = 0; t0 < P.gb.GS; t0 += P.phase_tiles) {
+        const int64_t nt = std::min<int64_t>(P.phase_tiles, P.gb.GS - t0);
+        const int64_t cols = std::min<int64_t>(nt * BNT, P.N - t0 * BNT);   // columns of this phase
+        m.ntile0 = t0;
+        m.n_ntiles = nt;
+        if (partials) {            // the phase's K planes: M x cols each
+            m.out = w + P.off_w;
+            m.ldo = cols;
+            m.plane = P.M * cols;
+            m.out_tile0 = t0;
+        } else {
+            m.out = out;
+            m.ldo = ldo;
+            m.plane = 0;
+            m.out_tile0 = 0;
+        }
+        {   // 32 workgroups per XCD: grp_v class members x grp_t column tiles
+            int64_t gt = 1;
+            while (gt * 2 <= 8 && gt * 2 <= nt) gt *= 2;
+            const int64_t members = (int64_t)P.Kt * P.ga.GS;
+            int64_t gv = 32 / gt;
+            while (gv > 1 && gv / 2 >= members) gv /= 2;
+            m.grp_t = gt; m.grp_v = gv;
+            m.n_tg = ceil_div(nt, gt);
+            m.n_ug = ceil_div(members, gv);
+        }
+        hipEvent_t ev0 = nullptr, ev1 = nullptr;
+        if (g_prof) {
+            if (hipEventCreate(&ev0) != hipSuccess || hipEventCreate(&ev1) != hipSuccess)
+                return HS_ERR_LAUNCH_FAILED;
+            (void)hipEventRecord(ev0, stream);
+        }
+        e = launch_mm(P.f.fam, P.f.form, m, stream);
+        if (g_prof) {
+            (void)hipEventRecord(ev1, stream);
+            g_events.push_back({ev0, ev1});
+        }
+        if (e != hipSuccess) return HS_ERR_LAUNCH_FAILED;
+        if (partials) {
+            uint8_t *c0 = (uint8_t *)out + (size_t)t0 * BNT * (f64 ? 8 : 4);
+            e = launch_backshift(f64, w + P.off_w, P.M * cols, P.K, P.M, cols, c0, ldo, stream);
+            if (e != hipSuccess) return HS_ERR_LAUNCH_FAILED;
+        }
     }
-    e = launch_mm(P.f.fam, P.f.form, m, stream);
-    if (g_prof) {
-        (void)hipEventRecord(ev1, stream);
-        g_events.push_back({ev0, ev1});
-    }
-    if (e != hipSuccess) return HS_ERR_LAUNCH_FAILED;
-    if (partials)
-        return launch_status(launch_backshift(f64, w + P.off_w, P.M * P.N, P.K, P.M, P.N, out, ldo, stream));
     return HS_OK;
 }
 

@@ -108,7 +108,9 @@ struct MainArgs {
     int64_t nch;             // chunks per contraction block
     int64_t S_r;             // stripe height
     int64_t M, N;
-    int64_t n_ntiles;
+    int64_t n_ntiles;        // column tiles of this launch: ntile0 .. ntile0 + n_ntiles - 1
+    int64_t ntile0;
+    int64_t out_tile0;       // column tile that lands at column 0 of out
     int out_f64;             // out element type: 1 double, 0 float
     // workgroup groups: grp_v class members x grp_t column tiles run together
     int64_t grp_v, grp_t, n_ug, n_tg;

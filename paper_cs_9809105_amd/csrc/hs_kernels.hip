@@ -611,6 +611,7 @@ void mm_kernel(MainArgs a) {
         msub = bid % a.GS;
         v = (int)(bid / a.GS);
     }
+    ntile += a.ntile0;                                  // column tile of the whole product
 
     const int p = a.p, K = a.K, MS = a.MS;
     const int64_t nch = a.nch;
@@ -842,7 +843,7 @@ void mm_kernel(MainArgs a) {
             const int64_t within = msub * MS + i;
             const int64_t row = (int64_t)((v - l + p) % p) * S_r + within;
             const bool rok = l < K && within < S_r && row < a.M;
-            const int64_t obase = (int64_t)l * a.plane + row * a.ldo + ntile * BN + wn * C::WN +
+            const int64_t obase = (int64_t)l * a.plane + row * a.ldo + (ntile - a.out_tile0) * BN + wn * C::WN +
                                   (FAM == FAM_F64 ? (lane & 15) : (lane & 31));
             const int64_t cbase = ntile * BN + wn * C::WN + (FAM == FAM_F64 ? (lane & 15) : (lane & 31));
 #pragma unroll
