@@ -580,3 +580,25 @@ def test_complex_autograd():
     assert err_row(C.detach().cpu().numpy().astype(np.complex128), oracle.complex_gemm(Ah, Bh)) <= 1e-5
     assert err_row(A.grad.cpu().numpy().astype(np.complex128), oracle.complex_gemm(Gh, np.conj(Bh).T)) <= 1e-5
     assert err_row(B.grad.cpu().numpy().astype(np.complex128), oracle.complex_gemm(np.conj(Ah).T, Gh)) <= 1e-5
+
+
+@pytest.mark.parametrize("dt", ["f32", "split3_bf16"])
+def test_many_column_phases(dt):
+    """M = 16384 with K = 8: each column tile's 8 partial planes take 128 MB,
+    so every 256-column tile is a phase of its own (8 phases, the last one
+    ragged), each back-shifted before the next reuses the planes."""
+    _skip_no_gpu()
+    m, k, n, p, K = 16384, 256, 2000, 64, 8
+    A, A64 = to_dev(inputs.normal((m, k), seed=1101), dt)
+    B, B64 = to_dev(inputs.normal((k, n), seed=1102), dt)
+    note("column phases", dt)
+    C = hs.hs_gemm(A, B, dtype=dt, p=p, K=K, out=poisoned((m, n), torch.float32))
+    torch.cuda.synchronize()
+    got = host(C)
+    assert not np.isnan(got).any()
+    rows = inputs.sample_rows(m, 64, seed=1103)
+    assert err_row(got[rows], oracle.gemm_rows(A64, B64, rows)) <= 1e-5
+    Ai, Ai64 = to_dev(inputs.small_int((m, k), seed=1104), dt)
+    Bi, Bi64 = to_dev(inputs.small_int((k, n), seed=1105), dt)
+    Ci = host(hs.hs_gemm(Ai, Bi, dtype=dt, p=p, K=K))
+    assert np.array_equal(Ci[rows], oracle.gemm_rows(Ai64, Bi64, rows))
