@@ -261,3 +261,15 @@ def test_complex_workspace_is_that_of_the_real_embedding():
         # backward: dA = G . B^H (m x 2k reals, contraction 2n), dB = A^H . G (k x 2n, contraction 2m)
         assert ws(B.HS_OP_BACKWARD, m, n, k, "c32", p, K) == max(ws(B.HS_OP_GEMM, m, 2 * k, 2 * n, "f32", p, K),
                                                                 ws(B.HS_OP_GEMM, k, 2 * n, 2 * m, "f32", p, K))
+
+
+def test_size_limits_are_reported_not_run():
+    """A packed operand must stay below 4 GiB (32-bit offsets in the main
+    kernel): just below passes the plan, just above is HS_ERR_NOT_SUPPORTED."""
+    ws = B.hs_workspace_size
+    # split A: 3 pieces x 32768 x 16384 x 2 bytes = 3 GiB
+    assert ws(B.HS_OP_GEMM, 32768, 256, 16384, "split3_bf16", 64, 2) != B.SIZE_MAX
+    # 3 pieces x 32768 x 24576 x 2 bytes = 4.5 GiB
+    assert ws(B.HS_OP_GEMM, 32768, 256, 24576, "split3_bf16", 64, 2) == B.SIZE_MAX
+    assert _gemm(m=32768, n=256, k=24576, dt=B.HS_SPLIT3_BF16, p=64, K=2, lda=24576, ldb=256,
+                 ldc=256) == B.HS_ERR_NOT_SUPPORTED

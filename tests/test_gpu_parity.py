@@ -602,3 +602,18 @@ def test_many_column_phases(dt):
     Bi, Bi64 = to_dev(inputs.small_int((k, n), seed=1105), dt)
     Ci = host(hs.hs_gemm(Ai, Bi, dtype=dt, p=p, K=K))
     assert np.array_equal(Ci[rows], oracle.gemm_rows(Ai64, Bi64, rows))
+
+
+def test_packed_operand_near_the_4gib_limit():
+    """Split A of 32768 x 16384: 3 GiB of packed pieces, addressed with the
+    main kernel's 32-bit offsets near their top."""
+    _skip_no_gpu()
+    m, k, n, p, K = 32768, 16384, 256, 64, 2
+    Ai, Ai64 = to_dev(inputs.small_int((m, k), seed=1201), "split3_bf16")
+    Bi, Bi64 = to_dev(inputs.small_int((k, n), seed=1202), "split3_bf16")
+    note("near 4 GiB packed operand")
+    C = host(hs.hs_gemm(Ai, Bi, dtype="split3_bf16", p=p, K=K))
+    rows = np.concatenate([inputs.sample_rows(m, 32, seed=1203), [0, m - 1]])
+    assert np.array_equal(C[rows], oracle.gemm_rows(Ai64, Bi64, rows))
+    del Ai, Bi
+    torch.cuda.empty_cache()
