@@ -84,6 +84,7 @@ struct Plan {
     OperandGeom ga, gb;
     size_t off_a, off_b, off_w, total;
     int64_t phase_tiles;              // column tiles per phase of the partial planes
+    int64_t a_span;                   // bytes of a workgroup's static-operand region
     size_t off_ea, off_eb;            // fp8: tile exponents of each operand
     int64_t tiles_k, tiles_ra, tiles_rb;
 };
@@ -128,27 +129,33 @@ hs_status make_plan(int64_t M, int64_t N, int64_t Kd, hs_dtype dt, hs_schedule s
     a.R = M; a.Kd = Kd; a.striped = 1; a.S_r = S_r; a.grp_rows = MS;
     a.GS = ceil_div(S_r, MS); a.n_groups = (int64_t)p * a.GS; a.p = p;
     a.S_k = S_k; a.nch = nch; a.chunk_bytes = CBY; a.pieces = NP;
-    a.piece_bytes = a.n_groups * p * nch * MS * CBY;
+    a.piece_bytes = (int64_t)p * nch * MS * CBY;
+    a.group_bytes = NP * a.piece_bytes;
+    a.wrap = P->K - 1;
 
     OperandGeom &b = P->gb;
     b.R = N; b.Kd = Kd; b.striped = 0; b.S_r = 0; b.grp_rows = BNT;
     b.GS = ceil_div(N, BNT); b.n_groups = b.GS; b.p = p;
     b.S_k = S_k; b.nch = nch; b.chunk_bytes = CBY; b.pieces = NP;
-    b.piece_bytes = b.n_groups * p * nch * BNT * CBY;
+    b.piece_bytes = (int64_t)p * nch * BNT * CBY;
+    b.group_bytes = NP * b.piece_bytes;
+    b.wrap = 0;
 
     // grid (with padding to whole workgroup groups) must fit in 32 bits
     const int64_t nwg = (int64_t)p * a.GS * b.GS * 2 + 64;
     if (nwg > std::numeric_limits<int32_t>::max()) return HS_ERR_NOT_SUPPORTED;
-    // the main kernel addresses each packed operand with 32-bit offsets
+    // a workgroup addresses its region of each packed operand with 32-bit
+    // offsets: K groups of the static operand, one group of the travelling
     const int64_t kMaxPacked = (int64_t)0xFFFFFFF0;
-    if (a.piece_bytes * NP > kMaxPacked || b.piece_bytes * NP > kMaxPacked) return HS_ERR_NOT_SUPPORTED;
+    P->a_span = ((int64_t)(P->K - 1) * a.GS + 1) * a.group_bytes;
+    if (P->a_span > kMaxPacked || b.group_bytes > kMaxPacked) return HS_ERR_NOT_SUPPORTED;
     // 32-bit indexing of the pack kernel and of the stage counter
     if (pack_units(a, 1) >= (int64_t)1 << 31 || pack_units(b, 1) >= (int64_t)1 << 31) return HS_ERR_NOT_SUPPORTED;
     if ((int64_t)P->Kt * nch >= (int64_t)1 << 31) return HS_ERR_NOT_SUPPORTED;
 
     size_t off = 0;
-    P->off_a = off; off = align_up(off + (size_t)(a.piece_bytes * NP));
-    P->off_b = off; off = align_up(off + (size_t)(b.piece_bytes * NP));
+    P->off_a = off; off = align_up(off + (size_t)((a.n_groups + (int64_t)a.wrap * a.GS) * a.group_bytes));
+    P->off_b = off; off = align_up(off + (size_t)(b.n_groups * b.group_bytes));
     P->off_w = off;
     // Partial planes (Sec. 6.2, cyclic mapping): the columns of C are
     // processed in phases of phase_tiles tiles, and the K partial planes hold
@@ -243,10 +250,9 @@ hs_status run_product(const Plan &P, const Operand &X, const Operand &Y, void *o
     if (e != hipSuccess) return HS_ERR_LAUNCH_FAILED;
 
     MainArgs m{};
-    m.A = w + P.off_a; m.a_piece = P.ga.piece_bytes;
-    m.B = w + P.off_b; m.b_piece = P.gb.piece_bytes;
-    m.a_bytes = P.ga.piece_bytes * P.ga.pieces;
-    m.b_bytes = P.gb.piece_bytes * P.gb.pieces;
+    m.A = w + P.off_a; m.a_piece = P.ga.piece_bytes; m.a_group = P.ga.group_bytes;
+    m.B = w + P.off_b; m.b_piece = P.gb.piece_bytes; m.b_group = P.gb.group_bytes;
+    m.a_span = P.a_span;
     m.p = P.p; m.K = P.K; m.Kt = P.Kt;
     m.MS = P.ga.grp_rows; m.GS = P.ga.GS; m.nch = P.ga.nch; m.S_r = P.ga.S_r;
     m.M = P.M; m.N = P.N; m.out_f64 = f64;

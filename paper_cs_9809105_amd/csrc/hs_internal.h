@@ -53,13 +53,16 @@ struct OperandGeom {
     int64_t S_r;      // stripe height (striped) -- ceil(R / p)
     int grp_rows;     // rows per group (MS or BN)
     int64_t GS;       // groups per stripe (striped) or total groups (tiles)
-    int64_t n_groups; // total groups
+    int64_t n_groups; // logical groups (p GS striped, GS otherwise)
     int p;
     int64_t S_k;      // contraction block length -- ceil(Kd / p)
     int64_t nch;      // chunks per block (padded)
     int chunk_bytes;  // 32 (f64, f32, 16-bit) or 64 (fp8)
     int pieces;       // planes written
-    int64_t piece_bytes;
+    int64_t piece_bytes;  // one piece of one group: p blocks x nch chunks x grp_rows x chunk_bytes
+    int64_t group_bytes;  // one group, all pieces
+    int wrap;         // striped: copies of the last `wrap` stripes are stored
+                      // ahead of stripe 0 (stripe s sits at position s + wrap)
 };
 
 struct PackArgs {
@@ -89,11 +92,13 @@ enum PackEmbed {
 };
 
 struct MainArgs {
-    const uint8_t *A;        // packed static operand, piece 0
-    int64_t a_piece;         // bytes between pieces
+    const uint8_t *A;        // packed static operand (layout [group][piece][block][chunk]...)
+    int64_t a_piece;         // bytes between pieces inside a group
+    int64_t a_group;         // bytes between groups
     const uint8_t *B;        // packed travelling operand
     int64_t b_piece;
-    int64_t a_bytes, b_bytes; // total packed bytes (all pieces), each < 4 GiB
+    int64_t b_group;
+    int64_t a_span;          // bytes one workgroup addresses from its first group, < 4 GiB
     const int32_t *a_exps;   // fp8 only: tile exponents of each operand
     const int32_t *b_exps;
     int64_t a_tiles_k, b_tiles_k;

@@ -254,19 +254,34 @@ __global__ __launch_bounds__(256) void pack_kernel(PackArgs a) {
         }
     }
     // chunk = UPR planes of 16 bytes per row: [plane][row][16 bytes]
-    const int64_t off = (((int64_t)grp * p + kb) * nch + ch) * gr * g.chunk_bytes + ((int64_t)half * gr + rr) * 16;
-    uint8_t *dst = (uint8_t *)a.dst + off;
+    // [group][piece][block][chunk][plane][row][16 bytes]; a striped group's
+    // position is shifted by the `wrap` copies ahead of stripe 0, and a group
+    // of the last `wrap` stripes is written a second time as its copy
+    const int64_t inner = ((int64_t)kb * nch + ch) * gr * g.chunk_bytes + ((int64_t)half * gr + rr) * 16;
+    const int64_t gpos = g.striped ? (int64_t)grp + (int64_t)g.wrap * g.GS : (int64_t)grp;
+    uint8_t *dst = (uint8_t *)a.dst + gpos * g.group_bytes + inner;
+    uint8_t *dst2 = nullptr;
+    if (g.striped && g.wrap > 0) {
+        const int64_t stripe = grp / g.GS;
+        if (stripe >= g.p - g.wrap)
+            dst2 = (uint8_t *)a.dst + ((stripe - g.p + g.wrap) * g.GS + grp % g.GS) * g.group_bytes + inner;
+    }
+    auto put = [&](int64_t at, const u32x4 &w) {
+        *(u32x4 *)(dst + at) = w;
+        if (dst2) *(u32x4 *)(dst2 + at) = w;
+    };
     if constexpr (KIND == PK_F64) {
-        *(double2 *)dst = make_double2(vals_d[0], vals_d[1]);
+        put(0, __builtin_bit_cast(u32x4, make_double2(vals_d[0], vals_d[1])));
     } else if constexpr (KIND == PK_F32) {
-        *(float4 *)dst = make_float4(vals_f[0], vals_f[1], vals_f[2], vals_f[3]);
+        put(0, u32x4{__float_as_uint(vals_f[0]), __float_as_uint(vals_f[1]), __float_as_uint(vals_f[2]),
+                     __float_as_uint(vals_f[3])});
     } else if constexpr (KIND == PK_B16) {
         u32x4 w;
         w[0] = vals_h[0] | ((uint32_t)vals_h[1] << 16);
         w[1] = vals_h[2] | ((uint32_t)vals_h[3] << 16);
         w[2] = vals_h[4] | ((uint32_t)vals_h[5] << 16);
         w[3] = vals_h[6] | ((uint32_t)vals_h[7] << 16);
-        *(u32x4 *)dst = w;
+        put(0, w);
     } else if constexpr (KIND == PK_FP8) {
         // all 16 elements of the unit lie in one 128 x 128 scale tile
         int e = 0, e1 = 0;
@@ -286,8 +301,8 @@ __global__ __launch_bounds__(256) void pack_kernel(PackArgs a) {
                 w1[i / 4] |= q1 << ((i % 4) * 8);
             }
         }
-        *(u32x4 *)dst = w0;
-        if (a.refine) *(u32x4 *)(dst + g.piece_bytes) = w1;
+        put(0, w0);
+        if (a.refine) put(g.piece_bytes, w1);
     } else {   // PK_SPLIT3: a0 = bf16(a), a1 = bf16(a - a0), a2 = bf16(a - a0 - a1)
         uint16_t p0[8], p1[8], p2[8];
 #pragma unroll
@@ -308,7 +323,7 @@ __global__ __launch_bounds__(256) void pack_kernel(PackArgs a) {
             w[1] = h[2] | ((uint32_t)h[3] << 16);
             w[2] = h[4] | ((uint32_t)h[5] << 16);
             w[3] = h[6] | ((uint32_t)h[7] << 16);
-            *(u32x4 *)(dst + q * g.piece_bytes) = w;
+            put(q * g.piece_bytes, w);
         }
     }
 }
@@ -618,11 +633,15 @@ void mm_kernel(MainArgs a) {
     const int spb = (int)(nch / CPS);                   // stages per contraction block
     const int nstages = a.Kt * spb;                     // host keeps this below 2^31
 
-    // per-thread load descriptors: byte offsets that do not depend on the
-    // step (group of the static operand, row, half-row, piece, chunk).  Units
-    // past the K groups (only when K * MS < BM) re-read offset 0: their tile
-    // rows are never stored.  The host guarantees every packed operand is
-    // below 4 GiB, so 32-bit offsets address it.
+    // Each workgroup addresses its own region of the packed operands with
+    // 32-bit offsets: for the static operand the K groups of stripes v, v-1,
+    // .., v-K+1, which sit at positions v .. v+K-1 (times GS) because copies
+    // of the last K-1 stripes precede stripe 0 (so no group wraps round the
+    // ring); for the travelling operand its group of BN columns.  The host
+    // keeps each region below 4 GiB, whatever the size of the operands.
+    // Per-thread load descriptors are offsets that do not depend on the step
+    // (group, row, half-row, piece, chunk); units past the K groups (only
+    // when K * MS < BM) re-read offset 0: their tile rows are never stored.
     uint32_t a_off[C::UA];
 #pragma unroll
     for (int q = 0; q < C::UA; ++q) {
@@ -632,8 +651,7 @@ void mm_kernel(MainArgs a) {
         const int plane = within / BM, rho = within % BM;
         const int P = slab / CPS, c = slab % CPS;
         const int l = rho / MS, i = rho % MS;
-        const int64_t grp = (int64_t)((v - l + p) % p) * a.GS + msub;
-        a_off[q] = l < K ? (uint32_t)((int64_t)P * a.a_piece + grp * (int64_t)p * nch * MS * C::CB +
+        a_off[q] = l < K ? (uint32_t)((int64_t)(K - 1 - l) * a.GS * a.a_group + (int64_t)P * a.a_piece +
                                       (int64_t)c * MS * C::CB + (int64_t)(plane * MS + i) * 16)
                          : 0u;
     }
@@ -644,11 +662,10 @@ void mm_kernel(MainArgs a) {
         const int slab = ui / (BN * C::NPL);
         const int within = ui % (BN * C::NPL);
         const int P = slab / CPS, c = slab % CPS;
-        b_off[q] = (uint32_t)((int64_t)P * a.b_piece + ntile * (int64_t)p * nch * BN * C::CB +
-                              (int64_t)c * BN * C::CB + (int64_t)within * 16);
+        b_off[q] = (uint32_t)((int64_t)P * a.b_piece + (int64_t)c * BN * C::CB + (int64_t)within * 16);
     }
-    const __amdgpu_buffer_rsrc_t rsA = packed_rsrc(a.A, (uint32_t)a.a_bytes);
-    const __amdgpu_buffer_rsrc_t rsB = packed_rsrc(a.B, (uint32_t)a.b_bytes);
+    const __amdgpu_buffer_rsrc_t rsA = packed_rsrc(a.A + ((int64_t)v * a.GS + msub) * a.a_group, (uint32_t)a.a_span);
+    const __amdgpu_buffer_rsrc_t rsB = packed_rsrc(a.B + ntile * a.b_group, (uint32_t)a.b_group);
 
     // Position of the next stage to fetch.  The steps of virtual processor
     // v visit the travelling blocks kb = (v + jK) mod p, j = 0..K~-1 (base
@@ -751,8 +768,7 @@ void mm_kernel(MainArgs a) {
         // stage ahead, one barrier per stage), which halves the LDS writes
         // and cuts the LDS reads by a third.
         const int r32 = lane & 31, g = lane >> 5;
-        const uint32_t b_lane = (uint32_t)(ntile * (int64_t)p * nch * BN * C::CB + (int64_t)g * BN * 16 +
-                                           (int64_t)(wn * C::WN + r32) * 16);
+        const uint32_t b_lane = (uint32_t)((int64_t)g * BN * 16 + (int64_t)(wn * C::WN + r32) * 16);
         const uint32_t b_piece = (uint32_t)a.b_piece;
         typedef u32x4 BQ[CPS][C::NP][C::TN];
         auto load_b = [&](BQ &bq, uint32_t ch) {

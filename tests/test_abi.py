@@ -264,12 +264,16 @@ def test_complex_workspace_is_that_of_the_real_embedding():
 
 
 def test_size_limits_are_reported_not_run():
-    """A packed operand must stay below 4 GiB (32-bit offsets in the main
-    kernel): just below passes the plan, just above is HS_ERR_NOT_SUPPORTED."""
+    """A workgroup addresses its region of each packed operand (K groups of
+    the static operand, one column group of the travelling one) with 32-bit
+    offsets, so operands far above 4 GiB are fine, but a region above 4 GiB
+    is HS_ERR_NOT_SUPPORTED."""
     ws = B.hs_workspace_size
-    # split A: 3 pieces x 32768 x 16384 x 2 bytes = 3 GiB
-    assert ws(B.HS_OP_GEMM, 32768, 256, 16384, "split3_bf16", 64, 2) != B.SIZE_MAX
-    # 3 pieces x 32768 x 24576 x 2 bytes = 4.5 GiB
-    assert ws(B.HS_OP_GEMM, 32768, 256, 24576, "split3_bf16", 64, 2) == B.SIZE_MAX
-    assert _gemm(m=32768, n=256, k=24576, dt=B.HS_SPLIT3_BF16, p=64, K=2, lda=24576, ldb=256,
+    # split A of 3 x 32768 x 24576 x 2 bytes = 4.5 GiB packed: fine
+    assert ws(B.HS_OP_GEMM, 32768, 256, 24576, "split3_bf16", 64, 2) != B.SIZE_MAX
+    # a column group of B: 3 pieces x 2^21 x 256 columns x 2 bytes = 3 GiB: fine
+    assert ws(B.HS_OP_GEMM, 4096, 256, 1 << 21, "split3_bf16", 64, 2) != B.SIZE_MAX
+    # 6 GiB: too large for one workgroup's offsets
+    assert ws(B.HS_OP_GEMM, 4096, 256, 1 << 22, "split3_bf16", 64, 2) == B.SIZE_MAX
+    assert _gemm(m=4096, n=256, k=1 << 22, dt=B.HS_SPLIT3_BF16, p=64, K=2, lda=1 << 22, ldb=256,
                  ldc=256) == B.HS_ERR_NOT_SUPPORTED

@@ -604,9 +604,9 @@ def test_many_column_phases(dt):
     assert np.array_equal(Ci[rows], oracle.gemm_rows(Ai64, Bi64, rows))
 
 
-def test_packed_operand_near_the_4gib_limit():
-    """Split A of 32768 x 16384: 3 GiB of packed pieces, addressed with the
-    main kernel's 32-bit offsets near their top."""
+def test_packed_operand_of_3gib():
+    """Split A of 32768 x 16384: 3 GiB of packed pieces, including the copies
+    of the last K - 1 stripes ahead of stripe 0."""
     _skip_no_gpu()
     m, k, n, p, K = 32768, 16384, 256, 64, 2
     Ai, Ai64 = to_dev(inputs.small_int((m, k), seed=1201), "split3_bf16")
@@ -616,4 +616,23 @@ def test_packed_operand_near_the_4gib_limit():
     rows = np.concatenate([inputs.sample_rows(m, 32, seed=1203), [0, m - 1]])
     assert np.array_equal(C[rows], oracle.gemm_rows(Ai64, Bi64, rows))
     del Ai, Bi
+    torch.cuda.empty_cache()
+
+
+def test_operand_above_4gib():
+    """FP32 A of 40960 x 32768 packs to 5.4 GB: more than 32-bit offsets
+    reach, so each workgroup addresses its own region of it (K stripe groups
+    of A, one column group of B).  Small integers, exact on sampled rows."""
+    _skip_no_gpu()
+    m, k, n, p, K = 40960, 32768, 256, 64, 2
+    g = inputs.rng(1301)
+    A8 = g.integers(-8, 9, size=(m, k), dtype=np.int8)
+    B64 = inputs.small_int((k, n), seed=1302)
+    A = torch.from_numpy(A8).cuda().float()
+    B = torch.from_numpy(B64).float().cuda()
+    note("operand above 4 GiB")
+    C = host(hs.hs_gemm(A, B, dtype="f32", p=p, K=K))
+    rows = np.concatenate([inputs.sample_rows(m, 24, seed=1303), [0, m - 1]])
+    assert np.array_equal(C[rows], oracle.gemm_rows(A8[rows].astype(np.float64), B64, np.arange(len(rows))))
+    del A, B
     torch.cuda.empty_cache()
