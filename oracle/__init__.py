@@ -8,13 +8,16 @@ What it computes is the plain definition the method reaches exactly
 (Sec. 3.1, Eq. PRODUCT): c_ij = sum_k a_ik b_kj in double precision, ascending
 k, plus the transposed product, the matrix-vector product and the gradient of
 L = sum(C * G), and the complex product (``complex_gemm``, by its real
-and imaginary parts).  See ``hs_oracle.c``.  ``ring`` holds a literal simulator of
+and imaginary parts).  ``nbody`` is the all-pairs gravitational sum, the
+prototype n^2-problem (Sec. 2.2) of the two-array recipe (Sec. 4.1).  See
+``hs_oracle.c``.  ``ring`` holds a literal simulator of
 Algorithms SYSTOLIC and HYPER-SYSTOLIC (Sec. 5) and ``bases`` the regular
 hyper-systolic bases (Sec. 4.4, Sec. 5.2.1); both pin the schedule.
 
 Parity pins: see tests/test_oracle.py (identity, permutation, small-integer
 exactness, explicit transpose, associativity, central differences, exactly
-rounded brute force).
+rounded brute force) and tests/test_oracle_nbody.py (a = -grad phi, momentum
+conservation, the virial identity, the field of a Plummer sphere, symmetry).
 """
 import ctypes
 import os
@@ -42,11 +45,13 @@ def _load():
         lib.hs_oracle_gemm_rows.argtypes = [i64, i64, dp, i64, dp, i64, ip, i64, dp, i64]
         lib.hs_oracle_gemm_tn_rows.argtypes = [i64, i64, dp, i64, dp, i64, ip, i64, dp, i64]
         lib.hs_oracle_grad_a_rows.argtypes = [i64, i64, dp, i64, dp, i64, ip, i64, dp, i64]
+        lib.hs_oracle_nbody.argtypes = [i64, dp, ctypes.c_double, dp, dp]
+        lib.hs_oracle_nbody_rows.argtypes = [i64, dp, ctypes.c_double, ip, i64, dp, dp]
         lib.hs_oracle_set_threads.argtypes = [ctypes.c_int]
         lib.hs_oracle_set_threads.restype = None
         for f in ("hs_oracle_gemm", "hs_oracle_gemm_tn", "hs_oracle_gemv",
                   "hs_oracle_backward", "hs_oracle_gemm_rows", "hs_oracle_gemm_tn_rows",
-                  "hs_oracle_grad_a_rows"):
+                  "hs_oracle_grad_a_rows", "hs_oracle_nbody", "hs_oracle_nbody_rows"):
             getattr(lib, f).restype = None
         _lib = lib
     return _lib
@@ -176,3 +181,32 @@ def complex_gemm_rows(A, B, rows):
     Ar, Ai, Br, Bi = A.real, A.imag, B.real, B.imag
     return ((gemm_rows(Ar, Br, rows) - gemm_rows(Ai, Bi, rows))
             + 1j * (gemm_rows(Ar, Bi, rows) + gemm_rows(Ai, Br, rows)))
+
+
+# ---------------------------------------------------------------------------
+# all-pairs n-body interaction (Sec. 2.2 prototype n^2-problem; Sec. 4.1)
+# ---------------------------------------------------------------------------
+def nbody(bodies, eps2, with_scale=False):
+    """(ax, ay, az, phi) of every body; bodies is n x 4 (x, y, z, m).
+
+    a_i = sum_{j != i} m_j d_ij / (|d_ij|^2 + eps2)^(3/2), d_ij = r_j - r_i;
+    phi_i = -sum_{j != i} m_j / (|d_ij|^2 + eps2)^(1/2).  With ``with_scale``
+    also returns sum_{j != i} |m_j d_ij| / (|d_ij|^2 + eps2)^(3/2)."""
+    X = _d(bodies)
+    n = X.shape[0]
+    assert X.shape == (n, 4)
+    out = np.empty((n, 4), np.float64)
+    sc = np.empty(n, np.float64)
+    _load().hs_oracle_nbody(n, _p(X), float(eps2), _p(out), _p(sc))
+    return (out, sc) if with_scale else out
+
+
+def nbody_rows(bodies, eps2, rows):
+    """(out, scale) of ``nbody`` for the bodies ``rows`` only."""
+    X = _d(bodies)
+    n = X.shape[0]
+    r, rp = _rows(rows)
+    out = np.empty((len(r), 4), np.float64)
+    sc = np.empty(len(r), np.float64)
+    _load().hs_oracle_nbody_rows(n, _p(X), float(eps2), rp, len(r), _p(out), _p(sc))
+    return out, sc

@@ -19,7 +19,7 @@ def build(force: bool = True) -> str:
     # -ffp-contract=off keeps a*b+s as two rounded operations (no FMA fusion),
     # so every element is the plain ascending-k sum of rounded products.
     cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp",
-           "-ffp-contract=off", "-fno-fast-math", "-o", LIB + ".tmp", SRC]
+           "-ffp-contract=off", "-fno-fast-math", "-o", LIB + ".tmp", SRC, "-lm"]
     subprocess.check_call(cmd)
     os.replace(LIB + ".tmp", LIB)
     return LIB

@@ -1,5 +1,6 @@
 /*
- * hs_oracle.c -- FP64 reference for the hyper-systolic matrix product.
+ * hs_oracle.c -- FP64 reference for the hyper-systolic matrix product and
+ * for the all-pairs n-body interaction (the n^2-problem, at the end).
  *
  * TEST INFRASTRUCTURE ONLY.  Nothing on the product path may include, link
  * or call this file; only the test-suite, the smoke check and the CPU
@@ -24,6 +25,7 @@
  * at a time in ascending p, so every element is bitwise the same sum as the
  * textbook i-j-p loop; only the memory walk differs.
  */
+#include <math.h>
 #include <stdint.h>
 #include <stddef.h>
 #include <omp.h>
@@ -188,4 +190,65 @@ void hs_oracle_grad_a_rows(int64_t n, int64_t k,
             out[t * ldo + p] = s;
         }
     }
+}
+
+/*
+ * All-pairs gravitational interaction of n bodies: the prototype
+ * n^2-problem of Sec. 2.2, which the two-array recipe of Sec. 4.1 computes as
+ * F_i = (+)_j f(x_i, z_j) with both data streams x and z equal to the bodies
+ * and (+) the sum.  With G = 1 and a softening eps2 >= 0, for body i at r_i:
+ *
+ *   a_i   =  sum_{j != i} m_j (r_j - r_i) / (|r_j - r_i|^2 + eps2)^(3/2)
+ *   phi_i = -sum_{j != i} m_j / (|r_j - r_i|^2 + eps2)^(1/2)
+ *
+ * (acceleration and potential at body i).  The definition written out:
+ * plain doubles, j ascending, one sequential sum per output element.
+ * bodies: n x 4 doubles (x, y, z, m); out: n x 4 (ax, ay, az, phi).
+ * scale (may be NULL): scale[i] = sum_{j != i} m_j |r_j - r_i| / s^(3/2), the
+ * sum of the lengths of the terms of a_i (the condition of that sum).
+ */
+static void nbody_one(int64_t n, const double *bodies, double eps2, int64_t i,
+                      double *o, double *scale)
+{
+    const double xi = bodies[4 * i], yi = bodies[4 * i + 1], zi = bodies[4 * i + 2];
+    double ax = 0.0, ay = 0.0, az = 0.0, phi = 0.0, sc = 0.0;
+    for (int64_t j = 0; j < n; ++j) {
+        if (j == i) continue;
+        const double dx = bodies[4 * j] - xi;
+        const double dy = bodies[4 * j + 1] - yi;
+        const double dz = bodies[4 * j + 2] - zi;
+        const double m = bodies[4 * j + 3];
+        const double s = dx * dx + dy * dy + dz * dz + eps2;
+        const double r = sqrt(s);
+        const double w = m / (s * r);
+        ax += w * dx;
+        ay += w * dy;
+        az += w * dz;
+        phi -= m / r;
+        sc += fabs(w) * sqrt(dx * dx + dy * dy + dz * dz);
+    }
+    o[0] = ax;
+    o[1] = ay;
+    o[2] = az;
+    o[3] = phi;
+    if (scale) *scale = sc;
+}
+
+void hs_oracle_nbody(int64_t n, const double *bodies, double eps2, double *out, double *scale)
+{
+    int64_t i;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (i = 0; i < n; ++i)
+        nbody_one(n, bodies, eps2, i, out + 4 * i, scale ? scale + i : NULL);
+}
+
+/* The same for the bodies rows[0..nrows-1] only (sampled parity at sizes
+ * where the full n^2 sum is too slow for the CPU). */
+void hs_oracle_nbody_rows(int64_t n, const double *bodies, double eps2,
+                          const int64_t *rows, int64_t nrows, double *out, double *scale)
+{
+    int64_t t;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (t = 0; t < nrows; ++t)
+        nbody_one(n, bodies, eps2, rows[t], out + 4 * t, scale ? scale + t : NULL);
 }

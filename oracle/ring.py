@@ -1,4 +1,5 @@
-"""Literal simulator of the systolic and hyper-systolic matrix products.
+"""Literal simulator of the systolic and hyper-systolic matrix products, and
+of the two-array hyper-systolic recipe (Sec. 4.1).
 
 TEST INFRASTRUCTURE ONLY (never imported by the product path).
 
@@ -220,3 +221,69 @@ def expected_terms(p, a_name="A", b_name="B"):
         for j in range(p):
             C[i, j] = Term(Counter({((a_name, i, k), (b_name, k, j)): 1 for k in range(p)}))
     return C
+
+
+# ----------------------------------------------------------------------------
+# the two-array recipe (Sec. 4.1) on the regular bases (Def. REGULARBASE2)
+# ----------------------------------------------------------------------------
+def cshift_1d(x, k, counter=None):
+    """One row of Eq. CSHIFT1: cell i receives the element of cell i + k."""
+    n = len(x)
+    out = np.empty(n, dtype=object)
+    for i in range(n):
+        out[i] = x[(i + k) % n]
+    if counter is not None:
+        counter.events += 1
+    return out
+
+
+def _cells(x):
+    """1D object array holding x's elements one per cell (blocks stay whole)."""
+    out = np.empty(len(x), dtype=object)
+    for i in range(len(x)):
+        out[i] = x[i]
+    return out
+
+
+def two_array(x, z, K, f, zero):
+    """F_i = sum_j f(x_i, z_j) on a ring of p = len(x) cells (Sec. 4.1).
+
+    Step by step as the recipe states it, with A = (0, 1, .., 1) (K - 1
+    ones) and B = (0, K, .., K) (K~ - 1 entries K), K K~ = p:
+      1. K replicas x^_t of x, each made from the previous one by a shift of
+         stride a_t (x^_0 = x);
+      2. z visits its K~ positions, moved by the strides b_t;
+      3. after each move of z, every cell adds f(x^_t, z) into the
+         intermediate result y^_t, t = 0..K-1;
+      4. a collector starts as y^_{K-1} and is moved by the inverse strides
+         -a_t, adding y^_{t-1} after each move.
+    Elements may be numbers or numpy blocks (one block of bodies per cell);
+    ``zero()`` makes a fresh zero result.  Returns (y, shift_count)."""
+    p = len(x)
+    assert len(z) == p and p % K == 0
+    Kt = p // K
+    a = [0] + [1] * (K - 1)
+    b = [0] + [K] * (Kt - 1)
+    cnt = ShiftCounter()
+    xh = [_cells(x)]
+    for t in range(1, K):
+        xh.append(cshift_1d(xh[-1], a[t], cnt))
+    yh = []
+    for t in range(K):
+        yt = np.empty(p, dtype=object)
+        for i in range(p):
+            yt[i] = zero()
+        yh.append(yt)
+    zc = _cells(z)
+    for j in range(Kt):
+        if j > 0:
+            zc = cshift_1d(zc, b[j], cnt)
+        for t in range(K):
+            for i in range(p):
+                yh[t][i] = yh[t][i] + f(xh[t][i], zc[i])
+    y = yh[K - 1]
+    for t in range(K - 1, 0, -1):
+        y = cshift_1d(y, -a[t], cnt)
+        for i in range(p):
+            y[i] = y[i] + yh[t - 1][i]
+    return y, cnt.events

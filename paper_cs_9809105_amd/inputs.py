@@ -14,6 +14,9 @@ Sec. 7; these stand in for them):
 * ``small_int``     -- i.i.d. integers in [lo, hi] (exact in every dtype used)
 * ``row_scaled``    -- N(0, 1) times a per-row scale 10**U[-3, 3), i.e. scales
                        log-uniform in [1e-3, 1e3]
+* ``plummer``       -- n bodies (x, y, z, m) drawn from a Plummer sphere, the
+                       standard model of a globular cluster (the application
+                       the paper names for the gravitational n^2-problem)
 """
 import numpy as np
 
@@ -47,3 +50,29 @@ def sample_rows(n_rows, count, seed):
     """``count`` distinct sorted row indices in [0, n_rows)."""
     count = min(count, n_rows)
     return np.sort(rng(seed).choice(n_rows, size=count, replace=False)).astype(np.int64)
+
+
+def plummer(n, seed, scale=1.0, total_mass=1.0, unequal=False, u_max=0.999):
+    """n x 4 array of bodies (x, y, z, m) from a Plummer sphere of scale
+    length ``scale``: the enclosed mass fraction u = r^3 / (r^2 + a^2)^(3/2)
+    is drawn uniformly in [0, u_max) (u_max < 1 cuts the far tail) and
+    inverted, r = a / sqrt(u^(-2/3) - 1); directions are isotropic.  Masses
+    are equal (total_mass / n) or, with ``unequal``, proportional to
+    U[0.5, 1.5) and normalised to total_mass."""
+    g = rng(seed)
+    u = g.uniform(0.0, u_max, size=n)
+    with np.errstate(divide="ignore"):
+        r = scale / np.sqrt(u ** (-2.0 / 3.0) - 1.0)
+    cos_t = g.uniform(-1.0, 1.0, size=n)
+    phi = g.uniform(0.0, 2.0 * np.pi, size=n)
+    sin_t = np.sqrt(1.0 - cos_t * cos_t)
+    out = np.empty((n, 4), np.float64)
+    out[:, 0] = r * sin_t * np.cos(phi)
+    out[:, 1] = r * sin_t * np.sin(phi)
+    out[:, 2] = r * cos_t
+    if unequal:
+        w = g.uniform(0.5, 1.5, size=n)
+        out[:, 3] = w * (total_mass / w.sum()) if n else w
+    else:
+        out[:, 3] = total_mass / max(n, 1)
+    return out
