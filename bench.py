@@ -22,6 +22,15 @@ sys.path.insert(0, ROOT)
 PEAK = {  # MI355X published dense peaks
     "bf16": 2516.6, "f16": 2516.6, "fp8": 5033.2, "f32": 157.3, "f64": 78.6, "hbm_gbs": 8000.0,
 }
+# The published FP32 vector peak (256 CUs x 256 flops per clock x 2.4 GHz)
+# is the ALU roofline of the n-body kernel.  It counts two FMAs per lane and
+# clock; plain (unpacked) FMAs measured 74.9 TFLOP/s on the chip, and every
+# kernel here leaves packed FP32 instructions out.
+VALU_F32_PEAK = PEAK["f32"]
+# flops of one body-body interaction: 3 differences, 3 FMAs for the squared
+# distance plus softening, 1 reciprocal square root, 4 products / differences
+# for the potential and the factor m / s^(3/2), 3 FMAs into the acceleration
+NBODY_FLOPS = 20
 MFMA_PRODUCTS = {"split3_bf16": 6, "bf16": 1, "f16": 1, "f32": 1, "f64": 1, "fp8_e4m3": 1, "fp8_e4m3_r1": 3}
 MFMA_PEAK_KEY = {"split3_bf16": "bf16", "bf16": "bf16", "f16": "f16", "f32": "f32", "f64": "f64",
                  "fp8_e4m3": "fp8", "fp8_e4m3_r1": "fp8"}
@@ -38,18 +47,25 @@ def parse():
     ap.add_argument("--inputs", default="rowscaled", choices=["rowscaled", "uniform"],
                     help="rowscaled: N(0,1) with log-uniform row scales; uniform: U[-1,1]")
     ap.add_argument("--p", type=int, default=64)
-    ap.add_argument("--K", type=int, default=2)
+    ap.add_argument("--K", type=int, default=None, help="K of the schedule (2; 8 for nbody)")
     ap.add_argument("--form", default="split3_bf16")
     ap.add_argument("--compare", default="f32", help="form timed beside the headline ('' to skip)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle baseline sample (0 to skip)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one plain 256 MiB device copy first (reference for HBM counters)")
-    ap.add_argument("--workload", default="step", choices=["step", "gemv", "complex"],
+    ap.add_argument("--workload", default="step", choices=["step", "gemv", "complex", "nbody"],
                     help="step: the fwd+bwd product step (default); gemv: y = A.x alone "
                          "(A n x n FP32, HBM-bound; reports GB/s); complex: C = A.B on n x n "
-                         "complex64 N(0,1) data (--form c32_split3_bf16 or c32, compared with c32)")
-    return ap.parse_args()
+                         "complex64 N(0,1) data (--form c32_split3_bf16 or c32, compared with c32); "
+                         "nbody: the all-pairs gravitational interaction of --bodies Plummer "
+                         "bodies (FP32, ALU-bound; p = 64, K = 8 unless given)")
+    ap.add_argument("--bodies", type=int, default=1 << 18, help="bodies of the nbody workload")
+    ap.add_argument("--eps2", type=float, default=1e-4, help="softening of the nbody workload")
+    a = ap.parse_args()
+    if a.K is None:
+        a.K = 8 if a.workload == "nbody" else 2
+    return a
 
 
 def step(hs, A, B, G, form, p, K):
@@ -209,6 +225,68 @@ def gemv_main(args):
         "cpu_baseline": cpu}))
 
 
+def nbody_main(args):
+    """The all-pairs gravitational interaction of n Plummer bodies (FP32):
+    one hs_nbody call per step (interaction kernel and back-shift).  The
+    interaction kernel is bound by the vector ALU: 20 flops per pair against
+    the FP32 vector peak."""
+    import torch
+    import paper_cs_9809105_amd as hs
+    from paper_cs_9809105_amd import inputs
+    n, p, K, eps2 = args.bodies, args.p, args.K, args.eps2
+    X64 = inputs.plummer(n, seed=inputs.BASE_SEED, unequal=False)
+    X = torch.from_numpy(X64).float().cuda()
+    out = torch.empty((n, 4), dtype=torch.float32, device="cuda")
+    for _ in range(args.warmup):
+        hs.hs_nbody(X, eps2, p=p, K=K, out=out)
+    torch.cuda.synchronize()
+    hs.hs_profile_begin()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        hs.hs_nbody(X, eps2, p=p, K=K, out=out)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern_ms, launches = hs.hs_profile_end()
+    pairs = float(n) * (n - 1)
+    avg = kern_ms / max(launches, 1)
+    achieved = NBODY_FLOPS * pairs / (avg * 1e-3) / 1e12
+    cpu = None
+    if args.cpu_seconds > 0:
+        import numpy as np
+        import oracle
+        Xh = X.cpu().double().numpy()
+        e2 = float(np.float32(eps2))
+        # calibrate on a small sample, then time one sample sized to last
+        # about --cpu-seconds
+        rows = 64
+        t1 = time.perf_counter()
+        oracle.nbody_rows(Xh, e2, inputs.sample_rows(n, rows, seed=9))
+        t_cal = time.perf_counter() - t1
+        rows = max(1, min(n, int(rows * args.cpu_seconds / max(t_cal, 1e-4))))
+        idx = inputs.sample_rows(n, rows, seed=9)
+        t1 = time.perf_counter()
+        oracle.nbody_rows(Xh, e2, idx)
+        t_cpu = time.perf_counter() - t1
+        cpu = {"value": rows * (n - 1) / t_cpu / 1e9, "unit": "Ginteractions/s", "kind": "oracle",
+               "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)),
+               "value_tflops": NBODY_FLOPS * rows * (n - 1) / t_cpu / 1e12,
+               "sample": "%d sampled bodies, each against all %d others (FP64 direct sum, %.1f s)"
+                         % (rows, n - 1, t_cpu)}
+    print(json.dumps({
+        "metric": "body-body interactions per second, all-pairs gravity of n=%d bodies (FP32)" % n,
+        "value": pairs * args.steps / wall / 1e9, "unit": "Ginteractions/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "two-array hyper-systolic all-pairs gravitational interaction, "
+                               "n=%d Plummer-sphere bodies, equal masses, eps2=%g" % (n, eps2),
+                   "n": n, "p": p, "K": K, "eps2": eps2, "form": "f32"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_F32_PEAK, "unit": "TFLOP/s",
+                     "frac": achieved / VALU_F32_PEAK, "traffic": None, "kernel": "nbody_kernel",
+                     "flops_per_interaction": NBODY_FLOPS, "avg_kernel_ms": avg, "launches": launches},
+        "cpu_baseline": cpu}))
+
+
 def complex_main(args):
     """The fwd+bwd step on n x n complex64 data: C = A . B, dA = G . B^H,
     dB = A^H . G, each run as one real product of (complex as reals) and a
@@ -289,6 +367,8 @@ def main():
         return gemv_main(args)
     if args.workload == "complex":
         return complex_main(args)
+    if args.workload == "nbody":
+        return nbody_main(args)
     import numpy as np
     import torch
     import paper_cs_9809105_amd as hs

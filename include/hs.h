@@ -116,7 +116,8 @@ typedef enum {
     HS_OP_GEMM = 0,
     HS_OP_GEMM_TN = 1,
     HS_OP_GEMV = 2,
-    HS_OP_BACKWARD = 3
+    HS_OP_BACKWARD = 3,
+    HS_OP_NBODY = 4          /* m = number of bodies; n, k ignored */
 } hs_op;
 
 /* p virtual processors on a logical ring, K * K~ = p (Sec. 5.2).
@@ -191,10 +192,37 @@ hs_status hs_gemm_backward(int64_t m, int64_t n, int64_t k, hs_dtype dtype, hs_s
                            void *dA, int64_t ldda, void *dB, int64_t lddb,
                            void *ws, size_t ws_bytes, void *stream);
 
+/* All-pairs gravitational interaction of n bodies: the prototype
+ * n^2-problem of Sec. 2.2, computed with the two-array hyper-systolic recipe
+ * of Sec. 4.1 on the regular bases of Def. REGULARBASE2 (both data streams
+ * are the bodies).  With G = 1, for every body i:
+ *
+ *   a_i   =  sum_{j != i} m_j (r_j - r_i) / (|r_j - r_i|^2 + eps2)^(3/2)
+ *   phi_i = -sum_{j != i} m_j / (|r_j - r_i|^2 + eps2)^(1/2)
+ *
+ * The bodies are cut into p blocks of ceil(n / p); virtual processor v holds
+ * the K replicas block (v + t) mod p, t < K (base A = (0, 1, .., 1)), the
+ * travelling block is (v + j K) mod p at step j < K~ (base B = (0, K, .., K)),
+ * and the K intermediate results of each body are combined in the
+ * collector's order y^0 + (y^1 + ( .. + y^{K-1})), in FP64.  That is
+ * 2K + K~ - 3 shifts on a real ring (Thm. GAIN2, Eq. COMPLEXR).
+ *
+ * bodies: n x 4 values (x, y, z, m), row-major, contiguous; out: n x 4
+ * (ax, ay, az, phi), written, never read; out must not overlap bodies.
+ * dtype HS_F32 (float; eps2 is rounded to float, rsqrt is the hardware's
+ * 1-ulp reciprocal square root) or HS_F64 (double; correctly rounded sqrt
+ * and divide).  Both pointers aligned to one body (16 bytes F32, 32 F64).
+ * eps2 >= 0 and finite; with eps2 == 0 no two distinct bodies may share a
+ * position (their term is infinite).  n == 0 is a no-op; n < 2^31.
+ * Workspace: hs_workspace_size(HS_OP_NBODY, n, 0, 0, dtype, s) bytes
+ * (K n 4 values; none for K == 1). */
+hs_status hs_nbody(int64_t n, hs_dtype dtype, hs_schedule s, const void *bodies, double eps2, void *out,
+                   void *ws, size_t ws_bytes, void *stream);
+
 /* Kernel timing for measurement.  Between hs_profile_begin() and
  * hs_profile_end(), every launch of the main kernel of any call made from
  * this process (the MFMA kernel of a product, the matrix-vector kernel of
- * hs_gemv) is bracketed by a pair of HIP events on its stream.
+ * hs_gemv, the interaction kernel of hs_nbody) is bracketed by a pair of HIP events on its stream.
  * hs_profile_end() waits for those events and returns the summed elapsed
  * milliseconds and the number of launches.  Not thread-safe; host only.
  * Returns HS_ERR_INVALID_VALUE if profiling was not begun. */

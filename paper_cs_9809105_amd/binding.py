@@ -20,7 +20,7 @@ DTYPES = {"f64": HS_F64, "f32": HS_F32, "bf16": HS_BF16, "f16": HS_F16,
 # hs_status
 HS_OK, HS_ERR_INVALID_VALUE, HS_ERR_NOT_SUPPORTED, HS_ERR_WORKSPACE_TOO_SMALL, HS_ERR_LAUNCH_FAILED = range(5)
 # hs_op
-HS_OP_GEMM, HS_OP_GEMM_TN, HS_OP_GEMV, HS_OP_BACKWARD = range(4)
+HS_OP_GEMM, HS_OP_GEMM_TN, HS_OP_GEMV, HS_OP_BACKWARD, HS_OP_NBODY = range(5)
 SIZE_MAX = ctypes.c_size_t(-1).value
 
 
@@ -64,6 +64,8 @@ def lib():
     L.hs_gemm_backward.argtypes = [i64, i64, i64, ctypes.c_int, hs_schedule, vp, i64, vp, i64,
                                    vp, i64, vp, i64, vp, i64, vp, sz, vp]
     L.hs_gemm_backward.restype = ctypes.c_int
+    L.hs_nbody.argtypes = [i64, ctypes.c_int, hs_schedule, vp, ctypes.c_double, vp, vp, sz, vp]
+    L.hs_nbody.restype = ctypes.c_int
     L.hs_profile_begin.argtypes = []
     L.hs_profile_begin.restype = ctypes.c_int
     L.hs_profile_end.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
@@ -250,3 +252,31 @@ def hs_gemm_backward(A, B, G, dtype="f32", p=1, K=0, need_a=True, need_b=True, s
                                 ws.data_ptr() if ws is not None else None, nb, _stream(stream))
     _check(st, "hs_gemm_backward")
     return dA, dB
+
+
+def hs_nbody(bodies, eps2=0.0, dtype=None, p=1, K=0, out=None, stream=None):
+    """(ax, ay, az, phi) of every body of ``bodies`` (n x 4: x, y, z, m), the
+    all-pairs gravitational interaction on the two-array schedule (p, K).
+    dtype: "f32" or "f64" (default: the tensor's)."""
+    torch = _torch()
+    if not isinstance(bodies, torch.Tensor) or bodies.device.type != "cuda":
+        raise TypeError("bodies must be a GPU tensor")
+    if bodies.dim() != 2 or bodies.shape[1] != 4:
+        raise ValueError("bodies must be n x 4 (x, y, z, m)")
+    if dtype is None:
+        dtype = {torch.float32: "f32", torch.float64: "f64"}.get(bodies.dtype)
+        if dtype is None:
+            raise TypeError("bodies must be float32 or float64")
+    dt = _dt(dtype)
+    if bodies.dtype != getattr(torch, IN_TYPES[dt]) or dt not in (HS_F32, HS_F64):
+        raise TypeError("bodies must be float32 (f32) or float64 (f64)")
+    bodies = bodies.contiguous()
+    n = bodies.shape[0]
+    o = torch.empty((n, 4), dtype=bodies.dtype, device=bodies.device) if out is None else out
+    if tuple(o.shape) != (n, 4) or o.dtype != bodies.dtype or (n and not o.is_contiguous()):
+        raise ValueError("out must be a contiguous n x 4 tensor of the bodies' dtype")
+    ws, nb = _workspace(hs_workspace_size(HS_OP_NBODY, n, 0, 0, dt, p, K), bodies.device)
+    st = lib().hs_nbody(n, dt, hs_schedule(p, K), bodies.data_ptr(), float(eps2), o.data_ptr(),
+                        ws.data_ptr() if ws is not None else None, nb, _stream(stream))
+    _check(st, "hs_nbody")
+    return o

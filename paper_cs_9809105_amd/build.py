@@ -13,7 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhs.so")
-SOURCES = [os.path.join(CSRC, "hs_kernels.hip"), os.path.join(CSRC, "hs_api.cpp")]
+SOURCES = [os.path.join(CSRC, "hs_kernels.hip"), os.path.join(CSRC, "hs_nbody.hip"),
+           os.path.join(CSRC, "hs_api.cpp")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -132,4 +132,14 @@ struct GemvArgs {
     int vec;                 // 1: 16-byte loads are legal
 };
 
+// All-pairs n-body interaction on the two-array recipe (hs_nbody.hip).
+struct NbodyArgs {
+    int64_t n;               // bodies
+    double eps2;             // softening, >= 0 (rounded to float for FP32)
+    int p, K, Kt;            // ring of p virtual processors, K * Kt == p
+    int S;                   // bodies per block, ceil(n / p)
+    int sub;                 // workgroups along one block: ceil(S / 256)
+    int tgroups;             // thread groups per position: K / KR
+};
+
 }  // namespace hs

@@ -277,3 +277,50 @@ def test_size_limits_are_reported_not_run():
     assert ws(B.HS_OP_GEMM, 4096, 256, 1 << 22, "split3_bf16", 64, 2) == B.SIZE_MAX
     assert _gemm(m=4096, n=256, k=1 << 22, dt=B.HS_SPLIT3_BF16, p=64, K=2, lda=1 << 22, ldb=256,
                  ldc=256) == B.HS_ERR_NOT_SUPPORTED
+
+
+# ---------------------------------------------------------------------------
+# hs_nbody: argument checks and workspace (no launch)
+# ---------------------------------------------------------------------------
+FAKE = 1 << 40          # a 256-aligned address that is never dereferenced
+
+
+def _nbody(n, dt=B.HS_F32, p=4, K=2, bodies=FAKE, eps2=0.0, out=FAKE + (1 << 32), ws=FAKE + (1 << 33),
+           nb=1 << 30):
+    return B.lib().hs_nbody(n, dt, B.hs_schedule(p, K), bodies, eps2, out, ws, nb, None)
+
+
+def test_nbody_workspace_is_k_partial_planes():
+    ws = B.hs_workspace_size
+    assert ws(B.HS_OP_NBODY, 1000, 0, 0, "f32", 16, 4) == 4 * 1000 * 16
+    assert ws(B.HS_OP_NBODY, 1000, 0, 0, "f64", 16, 4) == 4 * 1000 * 32
+    assert ws(B.HS_OP_NBODY, 1000, 0, 0, "f32", 16, 1) == 0          # systolic: writes out directly
+    assert ws(B.HS_OP_NBODY, 1001, 0, 0, "f32", 8, 2) % 256 == 0
+    assert ws(B.HS_OP_NBODY, 0, 0, 0, "f32", 8, 2) == 0
+    assert ws(B.HS_OP_NBODY, 100, 0, 0, "bf16", 8, 2) == B.SIZE_MAX
+    assert ws(B.HS_OP_NBODY, -1, 0, 0, "f32", 8, 2) == B.SIZE_MAX
+    assert ws(B.HS_OP_NBODY, 100, 0, 0, "f32", 8, 3) == B.SIZE_MAX
+    assert ws(B.HS_OP_NBODY, 1 << 31, 0, 0, "f32", 8, 2) == B.SIZE_MAX
+
+
+def test_nbody_rejects_bad_arguments():
+    E = B.HS_ERR_INVALID_VALUE
+    assert _nbody(0) == B.HS_OK                                    # nothing to do
+    assert _nbody(10, dt=B.HS_BF16) == B.HS_ERR_NOT_SUPPORTED
+    assert _nbody(10, dt=B.HS_SPLIT3_BF16) == B.HS_ERR_NOT_SUPPORTED
+    assert _nbody(-1) == E
+    assert _nbody(10, p=6, K=4) == E                               # K must divide p
+    assert _nbody(10, eps2=-1e-3) == E
+    assert _nbody(10, eps2=float("nan")) == E
+    assert _nbody(10, eps2=float("inf")) == E
+    assert _nbody(10, eps2=1e39) == E                              # not a float
+    assert _nbody(10, bodies=None) == E
+    assert _nbody(10, out=None) == E
+    assert _nbody(10, bodies=FAKE + 8) == E                        # one body = 16 bytes
+    assert _nbody(10, dt=B.HS_F64, bodies=FAKE + 16) == E          # one body = 32 bytes
+    assert _nbody(10, out=FAKE + 16 * 9) == E                      # overlaps the bodies
+    assert _nbody(10, out=FAKE - 16 * 9) == E
+    assert _nbody(10, ws=None) == B.HS_ERR_WORKSPACE_TOO_SMALL
+    assert _nbody(10, nb=2 * 10 * 16 - 1) == B.HS_ERR_WORKSPACE_TOO_SMALL
+    assert _nbody(10, ws=FAKE + (1 << 33) + 64) == E               # workspace alignment
+    assert _nbody(1 << 31, ws=None, nb=0, K=1) == B.HS_ERR_NOT_SUPPORTED

@@ -34,3 +34,14 @@ def test_traffic_record_used_only_for_same_sources_and_workload(tmp_path, monkey
     assert bench.recorded_traffic("split3_bf16", 8192, 8192, 8192, 64, 2) is None   # kernels changed
     monkeypatch.setattr(bench, "TRAFFIC_RECORD", str(tmp_path / "missing.json"))
     assert bench.recorded_traffic("split3_bf16", 8192, 8192, 8192, 64, 2) is None
+
+
+def test_default_schedule_per_workload(monkeypatch):
+    monkeypatch.setattr(sys, "argv", ["bench.py"])
+    assert bench.parse().K == 2
+    monkeypatch.setattr(sys, "argv", ["bench.py", "--workload", "nbody"])
+    a = bench.parse()
+    assert (a.K, a.p, a.bodies) == (8, 64, 1 << 18)
+    monkeypatch.setattr(sys, "argv", ["bench.py", "--workload", "nbody", "--K", "4"])
+    assert bench.parse().K == 4
+    assert bench.VALU_F32_PEAK == 157.3
