@@ -85,9 +85,11 @@ extern "C" {
  *                  2 x 2 block (t, j) is [[re, im], [-im, re]] of b_tj, C
  *                  written as m x 2n = interleaved complex.  4 real
  *                  multiplications per complex one (no 3M rewrite: it
- *                  cancels).  Also hs_gemm_backward (dA = G B^H, dB = A^H G).
+ *                  cancels).  Also hs_gemm_tn (A^T as m x 2k reals, no
+ *                  conjugation), hs_gemv (FP32 complex arithmetic) and
+ *                  hs_gemm_backward (dA = G B^H, dB = A^H G).
  *  HS_C32_SPLIT3_BF16  the same with the split-BF16 arithmetic of
- *                  HS_SPLIT3_BF16 (FP32-accurate).  hs_gemm and
+ *                  HS_SPLIT3_BF16 (FP32-accurate).  hs_gemm, hs_gemm_tn and
  *                  hs_gemm_backward. */
 typedef enum {
     HS_F64 = 0,
@@ -162,7 +164,9 @@ hs_status hs_gemm(int64_t m, int64_t n, int64_t k, hs_dtype dtype, hs_schedule s
 /* C[m, n] = A^T . B with A stored k x m (lda >= m), B k x n (ldb >= n).
  * The transposed product the paper says runs "on the same footing" (Abstract,
  * Sec. 8): the same schedule, with A's tiles read along its columns.
- * All dtypes. */
+ * All dtypes; for the complex ones C = A^T B (transposed, not conjugated),
+ * sizes and ld* in complex elements, pointers 8-byte aligned, and the
+ * workspace of the real product m x 2k times 2k x 2n. */
 hs_status hs_gemm_tn(int64_t m, int64_t n, int64_t k, hs_dtype dtype, hs_schedule s,
                      const void *A, int64_t lda, const void *B, int64_t ldb,
                      void *C, int64_t ldc, void *ws, size_t ws_bytes, void *stream);
@@ -170,7 +174,9 @@ hs_status hs_gemm_tn(int64_t m, int64_t n, int64_t k, hs_dtype dtype, hs_schedul
 /* y[m] = A[m, n] . x[n]  (the matrix-vector product of the Abstract and
  * Sec. 8).  Virtual processor v owns row stripe v of A and y; x stripes
  * travel in the order of base A; the K partial vectors are combined in the
- * back-shift order, in FP64 for HS_F32.  dtype: HS_F32 or HS_F64.  lda >= n.
+ * back-shift order, in FP64 for HS_F32.  dtype: HS_F32, HS_F64 or HS_C32
+ * (complex64 A, x, y; lda in complex elements; pointers 8-byte aligned; the
+ * real and imaginary partial sums combined in FP64).  lda >= n.
  * Needs no workspace (ws may be NULL). */
 hs_status hs_gemv(int64_t m, int64_t n, hs_dtype dtype, hs_schedule s,
                   const void *A, int64_t lda, const void *x, void *y,

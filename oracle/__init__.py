@@ -174,6 +174,14 @@ def complex_gemm(A, B):
     return (gemm(Ar, Br) - gemm(Ai, Bi)) + 1j * (gemm(Ar, Bi) + gemm(Ai, Br))
 
 
+def complex_gemv(A, x):
+    """y = A . x for complex A (m x n) and x (n), in FP64 parts."""
+    A = np.asarray(A, np.complex128)
+    x = np.asarray(x, np.complex128)
+    Ar, Ai, xr, xi = A.real, A.imag, x.real, x.imag
+    return (gemv(Ar, xr) - gemv(Ai, xi)) + 1j * (gemv(Ar, xi) + gemv(Ai, xr))
+
+
 def complex_gemm_rows(A, B, rows):
     """Rows ``rows`` of the complex product A . B."""
     A = np.asarray(A, np.complex128)

@@ -419,11 +419,17 @@ size_t hs_workspace_size(hs_op op, int64_t m, int64_t n, int64_t k, hs_dtype dty
             if (make_plan(m, n, k, dtype, s, &P) != HS_OK) return bad;
             return P.total;
         }
-        case HS_OP_GEMM_TN:
+        case HS_OP_GEMM_TN: {
+            hs_dtype base;
+            if (complex_base(dtype, &base)) {
+                if (m < 0 || n < 0 || k < 0 || make_plan(m, 2 * n, 2 * k, base, s, &P) != HS_OK) return bad;
+                return P.total;
+            }
             if (make_plan(m, n, k, dtype, s, &P) != HS_OK) return bad;
             return P.total;
+        }
         case HS_OP_GEMV: {
-            if (dtype != HS_F32 && dtype != HS_F64) return bad;
+            if (dtype != HS_F32 && dtype != HS_F64 && dtype != HS_C32) return bad;
             hs_schedule r;
             if (hs_schedule_resolve(s, &r) != HS_OK || m < 0 || n < 0) return bad;
             return 0;
@@ -480,6 +486,19 @@ hs_status hs_gemm(int64_t m, int64_t n, int64_t k, hs_dtype dtype, hs_schedule s
 hs_status hs_gemm_tn(int64_t m, int64_t n, int64_t k, hs_dtype dtype, hs_schedule s,
                      const void *A, int64_t lda, const void *B, int64_t ldb,
                      void *C, int64_t ldc, void *ws, size_t ws_bytes, void *stream) {
+    hs_dtype base;
+    if (complex_base(dtype, &base)) {
+        // A^T as m x 2k reals, read along A's columns; B embedded as 2k x 2n
+        if (m < 0 || n < 0 || k < 0) return HS_ERR_INVALID_VALUE;
+        Plan P;
+        HS_TRY(make_plan(m, 2 * n, 2 * k, base, s, &P));
+        HS_TRY(check_mat(A, k, m, lda, 8));
+        HS_TRY(check_mat(B, k, n, ldb, 8));
+        HS_TRY(check_mat(C, m, n, ldc, 8));
+        HS_TRY(check_ws(P, ws, ws_bytes));
+        return run_product(P, Operand{A, 2 * lda, 0, EMB_TRANS}, Operand{B, 2 * ldb, 0, EMB_BLOCKS}, C, 2 * ldc, ws,
+                           (hipStream_t)stream);
+    }
     Plan P;
     HS_TRY(make_plan(m, n, k, dtype, s, &P));
     HS_TRY(check_mat(A, k, m, lda, P.f.in_esz));
@@ -494,24 +513,26 @@ hs_status hs_gemv(int64_t m, int64_t n, hs_dtype dtype, hs_schedule s,
                   void *ws, size_t ws_bytes, void *stream) {
     (void)ws;
     (void)ws_bytes;
-    if (dtype != HS_F32 && dtype != HS_F64) return HS_ERR_NOT_SUPPORTED;
+    if (dtype != HS_F32 && dtype != HS_F64 && dtype != HS_C32) return HS_ERR_NOT_SUPPORTED;
     hs_schedule r;
     HS_TRY(hs_schedule_resolve(s, &r));
-    const size_t esz = dtype == HS_F64 ? 8 : 4;
+    const int cplx = dtype == HS_C32;
+    const size_t esz = dtype == HS_F32 ? 4 : 8;
     HS_TRY(check_mat(A, m, n, lda, esz));
     if (n > 0 && m > 0 && (!x || !aligned(x, esz))) return HS_ERR_INVALID_VALUE;
     if (m > 0 && (!y || !aligned(y, esz))) return HS_ERR_INVALID_VALUE;
     if (m == 0) return HS_OK;
     hipStream_t st = (hipStream_t)stream;
     const int f64 = dtype == HS_F64;
-    if (n == 0) return launch_status(launch_fill_zero(f64, y, m, 1, 1, st));
+    if (n == 0) return launch_status(cplx ? launch_fill_zero(0, y, m, 2, 2, st) : launch_fill_zero(f64, y, m, 1, 1, st));
     GemvArgs g{};
+    g.cplx = cplx;
     g.A = A; g.lda = lda; g.x = x; g.y = y; g.m = m; g.n = n;
     g.p = r.p; g.K = r.K; g.Kt = r.p / r.K;
     g.S_r = std::max<int64_t>(1, ceil_div(m, r.p));
     g.S_k = std::max<int64_t>(1, ceil_div(n, r.p));
     if (g.S_k * r.p >= ((int64_t)1 << 31)) return HS_ERR_NOT_SUPPORTED;   // 32-bit positions
-    const int VE = f64 ? 2 : 4;
+    const int VE = (f64 || cplx) ? 2 : 4;         // elements per 16-byte load
     g.vec = (g.S_k % VE == 0 && lda % VE == 0 && n % VE == 0 && aligned(A, 16) && aligned(x, 16)) ? 1 : 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (g_prof) {

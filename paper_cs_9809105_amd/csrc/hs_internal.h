@@ -87,8 +87,9 @@ enum PackEmbed {
                        // 2 x 2 block embedding [[re x, im x], [-im x, re x]]
     EMB_BLOCKS_H = 2,  // K-major source X[t][j] (t = row/2, j = kk/2): the block
                        // embedding of conj(X[t][j]), i.e. of X^H
-    EMB_CONJ = 3       // MN-major source X[i][t] (i = kk/2, t = row): conj(X)^T
+    EMB_CONJ = 3,      // MN-major source X[i][t] (i = kk/2, t = row): conj(X)^T
                        // as reals, kk = 2i + (0 re, 1 im)
+    EMB_TRANS = 4      // the same read without the conjugation: X^T as reals
 };
 
 struct MainArgs {
@@ -130,6 +131,7 @@ struct GemvArgs {
     int p, K, Kt;
     int64_t S_r, S_k;
     int vec;                 // 1: 16-byte loads are legal
+    int cplx;                // 1: complex64 A, x, y (lda in complex elements)
 };
 
 // All-pairs n-body interaction on the two-array recipe (hs_nbody.hip).

@@ -243,9 +243,9 @@ __global__ __launch_bounds__(256) void pack_kernel(PackArgs a) {
                     // conj(x): the im entries change sign
                     idx = (row >> 1) * a.ld + 2 * (kk >> 1) + (sr ^ c);
                     neg = sr == 0 && c == 1;
-                } else if (!KMAJOR && a.embed == EMB_CONJ) {
+                } else if (!KMAJOR && (a.embed == EMB_CONJ || a.embed == EMB_TRANS)) {
                     idx = (kk >> 1) * a.ld + 2 * row + sr;
-                    neg = sr == 1;
+                    neg = a.embed == EMB_CONJ && sr == 1;
                 }
             }
             if constexpr (KIND == PK_F64) vals_d[e] = ok ? (double)src[idx] : 0.0;
@@ -992,6 +992,78 @@ __global__ __launch_bounds__(256) void gemv_kernel(GemvArgs a) {
     if (lane == 0) ((T *)a.y)[row] = (T)S;
 }
 
+// Complex y = A x (complex64, interleaved re/im): the map and collector
+// order of gemv_kernel, positions in complex elements; each lane keeps the
+// real and imaginary partial sums, combined in FP64 in the back-shift order.
+// VE complex elements per load: 2 (16 bytes) or 1.
+template <int VE>
+__global__ __launch_bounds__(256) void gemv_c32_kernel(GemvArgs a) {
+    typedef typename std::conditional<VE == 2, float4, float2>::type V;
+    constexpr int U = 4;                       // loads in flight per lane
+    const int lane = threadIdx.x & 63;
+    const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (row >= a.m) return;
+    const float *Ar = (const float *)a.A + row * a.lda * 2;
+    const float *x = (const float *)a.x;
+    const int p = a.p, K = a.K;
+    const int rs = (int)(row / a.S_r);
+    const int S_k = (int)a.S_k;                // host: S_k * p fits in 32 bits
+    const int total = a.Kt * S_k;
+    double Sr = 0.0, Si = 0.0;
+    for (int l = K - 1; l >= 0; --l) {         // collector: c^{K-1} first
+        const int v = (rs + l) % p;
+        int e = lane * VE, j = e / S_k, off = e % S_k;
+        int kb = (int)(((int64_t)v + (int64_t)j * K) % p);
+        auto advance = [&]() {
+            e += 64 * VE;
+            off += 64 * VE;
+            while (off >= S_k) {
+                off -= S_k;
+                kb += K;
+                if (kb >= p) kb -= p;
+            }
+        };
+        float re = 0.f, im = 0.f;
+        while (e < total) {
+            V av[U], xv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t col = (int64_t)kb * S_k + off;
+                const bool ok = e < total && col < a.n;
+                if (ok) {
+                    av[u] = *(const V *)(Ar + 2 * col);
+                    xv[u] = *(const V *)(x + 2 * col);
+                } else {
+                    av[u] = V{};
+                    xv[u] = V{};
+                }
+                advance();
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                re = __builtin_fmaf(av[u].x, xv[u].x, re);
+                re = __builtin_fmaf(-av[u].y, xv[u].y, re);
+                im = __builtin_fmaf(av[u].x, xv[u].y, im);
+                im = __builtin_fmaf(av[u].y, xv[u].x, im);
+                if constexpr (VE == 2) {
+                    re = __builtin_fmaf(av[u].z, xv[u].z, re);
+                    re = __builtin_fmaf(-av[u].w, xv[u].w, re);
+                    im = __builtin_fmaf(av[u].z, xv[u].w, im);
+                    im = __builtin_fmaf(av[u].w, xv[u].z, im);
+                }
+            }
+        }
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) {
+            re += __shfl_xor(re, m, 64);
+            im += __shfl_xor(im, m, 64);
+        }
+        Sr = (double)re + Sr;
+        Si = (double)im + Si;
+    }
+    if (lane == 0) ((float2 *)a.y)[row] = make_float2((float)Sr, (float)Si);
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -1115,7 +1187,10 @@ hipError_t launch_fill_zero(int f64, void *Cout, int64_t M, int64_t N, int64_t l
 hipError_t launch_gemv(int f64, const GemvArgs &a, hipStream_t st) {
     const unsigned nb = (unsigned)((a.m + 3) / 4);
     if (nb == 0) return hipSuccess;
-    if (f64) {
+    if (a.cplx) {
+        if (a.vec) hipLaunchKernelGGL((gemv_c32_kernel<2>), dim3(nb), dim3(256), 0, st, a);
+        else hipLaunchKernelGGL((gemv_c32_kernel<1>), dim3(nb), dim3(256), 0, st, a);
+    } else if (f64) {
         if (a.vec) hipLaunchKernelGGL((gemv_kernel<double, 2>), dim3(nb), dim3(256), 0, st, a);
         else hipLaunchKernelGGL((gemv_kernel<double, 1>), dim3(nb), dim3(256), 0, st, a);
     } else {

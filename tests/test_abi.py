@@ -234,14 +234,21 @@ def test_profile_end_without_begin():
     assert B.lib().hs_profile_end(None, None) == B.HS_ERR_INVALID_VALUE
 
 
-def test_complex_forms_are_product_and_backward_only():
+def test_complex_forms_argument_checks():
     L = B.lib()
     s = B.hs_schedule(2, 0)
     for dt in (B.HS_C32, B.HS_C32_SPLIT3_BF16):
-        assert L.hs_gemm_tn(8, 8, 8, dt, s, FAKE, 8, FAKE, 8, FAKE, 8, FAKE, 1 << 30, None) == B.HS_ERR_NOT_SUPPORTED
-        assert L.hs_gemv(8, 8, dt, s, FAKE, 8, FAKE, FAKE, None, 0, None) == B.HS_ERR_NOT_SUPPORTED
-        for op in (B.HS_OP_GEMM_TN, B.HS_OP_GEMV):
-            assert B.hs_workspace_size(op, 64, 64, 64, dt, 4) == B.SIZE_MAX
+        # transposed product: checks in complex elements, before any launch
+        tn = [8, 8, 8, dt, s, FAKE, 8, FAKE, 8, FAKE, 8, FAKE, 1 << 30, None]
+        bad = list(tn)
+        bad[5] = FAKE + 4                      # A not 8-byte aligned
+        assert L.hs_gemm_tn(*bad) == B.HS_ERR_INVALID_VALUE
+        bad = list(tn)
+        bad[6] = 7                             # lda < m (A is k x m)
+        assert L.hs_gemm_tn(*bad) == B.HS_ERR_INVALID_VALUE
+        bad = list(tn)
+        bad[12] = 8
+        assert L.hs_gemm_tn(*bad) == B.HS_ERR_WORKSPACE_TOO_SMALL
         # backward: argument checks in complex elements, before any launch
         args = [8, 8, 8, dt, s, FAKE, 8, FAKE, 8, FAKE, 8, FAKE, 8, FAKE, 8, FAKE, 1 << 30, None]
         bad = list(args)
@@ -250,6 +257,20 @@ def test_complex_forms_are_product_and_backward_only():
         bad = list(args)
         bad[16] = 8
         assert L.hs_gemm_backward(*bad) == B.HS_ERR_WORKSPACE_TOO_SMALL
+    # matrix-vector: complex64 in FP32 arithmetic only
+    gv = [8, 8, B.HS_C32, s, FAKE, 8, FAKE, FAKE, None, 0, None]
+    assert L.hs_gemv(8, 8, B.HS_C32_SPLIT3_BF16, s, FAKE, 8, FAKE, FAKE, None, 0, None) == B.HS_ERR_NOT_SUPPORTED
+    bad = list(gv)
+    bad[4] = FAKE + 4                          # A not 8-byte aligned
+    assert L.hs_gemv(*bad) == B.HS_ERR_INVALID_VALUE
+    bad = list(gv)
+    bad[5] = 7                                 # lda < n
+    assert L.hs_gemv(*bad) == B.HS_ERR_INVALID_VALUE
+    bad = list(gv)
+    bad[6] = FAKE + 4                          # x not 8-byte aligned
+    assert L.hs_gemv(*bad) == B.HS_ERR_INVALID_VALUE
+    assert B.hs_workspace_size(B.HS_OP_GEMV, 64, 64, 0, "c32", 4) == 0
+    assert B.hs_workspace_size(B.HS_OP_GEMV, 64, 64, 0, "c32_split3_bf16", 4) == B.SIZE_MAX
 
 
 def test_complex_workspace_is_that_of_the_real_embedding():
@@ -258,6 +279,7 @@ def test_complex_workspace_is_that_of_the_real_embedding():
         assert ws(B.HS_OP_GEMM, m, n, k, "c32", p, K) == ws(B.HS_OP_GEMM, m, 2 * n, 2 * k, "f32", p, K)
         assert ws(B.HS_OP_GEMM, m, n, k, "c32_split3_bf16", p, K) == \
             ws(B.HS_OP_GEMM, m, 2 * n, 2 * k, "split3_bf16", p, K)
+        assert ws(B.HS_OP_GEMM_TN, m, n, k, "c32", p, K) == ws(B.HS_OP_GEMM_TN, m, 2 * n, 2 * k, "f32", p, K)
         # backward: dA = G . B^H (m x 2k reals, contraction 2n), dB = A^H . G (k x 2n, contraction 2m)
         assert ws(B.HS_OP_BACKWARD, m, n, k, "c32", p, K) == max(ws(B.HS_OP_GEMM, m, 2 * k, 2 * n, "f32", p, K),
                                                                 ws(B.HS_OP_GEMM, k, 2 * n, 2 * m, "f32", p, K))

@@ -501,6 +501,70 @@ def test_complex_gaussian_integers_bit_exact(dt):
     assert np.array_equal(C.cpu().numpy().astype(np.complex128), oracle.complex_gemm(Ah, Bh))
 
 
+@pytest.mark.parametrize("dt", CPLX)
+@pytest.mark.parametrize("case", CPLX_CASES)
+def test_complex_transposed_product(dt, case):
+    """C = A^T B (transposed, not conjugated), A stored k x m."""
+    _skip_no_gpu()
+    m, n, k, p, K = case
+    A, Ah = _cplx_dev((k, m), 1950 + m)
+    B, Bh = _cplx_dev((k, n), 1960 + n)
+    out = poisoned((m, n), torch.complex64)
+    note("complex tn", dt, case)
+    C = hs.hs_gemm_tn(A, B, dtype=dt, p=p, K=K, out=out)
+    torch.cuda.synchronize()
+    got = C.cpu().numpy().astype(np.complex128)
+    assert not np.isnan(got).any()
+    e = err_row(got, oracle.complex_gemm(Ah.T, Bh))
+    assert e <= 1e-5, (dt, case, e)
+
+
+@pytest.mark.parametrize("dt", CPLX)
+def test_complex_transposed_gaussian_integers_bit_exact(dt):
+    _skip_no_gpu()
+    m, n, k = 200, 136, 264
+    A, Ah = _cplx_dev((k, m), 1970, inputs.small_int)
+    B, Bh = _cplx_dev((k, n), 1972, inputs.small_int)
+    note("complex tn small int", dt)
+    C = hs.hs_gemm_tn(A, B, dtype=dt, p=8, K=2)
+    torch.cuda.synchronize()
+    assert np.array_equal(C.cpu().numpy().astype(np.complex128), oracle.complex_gemm(Ah.T, Bh))
+
+
+# (m, n, p, K): the 8192^2 workload, ragged stripes and blocks, odd n (8-byte
+# loads), the systolic case, K = p
+CGEMV_CASES = [(8192, 8192, 64, 8), (1000, 778, 12, 3), (33, 17, 4, 2), (64, 64, 1, 1), (256, 300, 16, 16)]
+
+
+@pytest.mark.parametrize("case", CGEMV_CASES)
+def test_complex_gemv(case):
+    _skip_no_gpu()
+    m, n, p, K = case
+    A, Ah = _cplx_dev((m, n), 2950 + m)
+    x, xh = _cplx_dev((n,), 2960 + n)
+    y = torch.full((m,), complex(float("nan"), float("nan")), dtype=torch.complex64, device="cuda")
+    note("complex gemv", case)
+    hs.hs_gemv(A, x, dtype="c32", p=p, K=K, out=y)
+    torch.cuda.synchronize()
+    got = y.cpu().numpy().astype(np.complex128)
+    assert not np.isnan(got).any()
+    assert err_row(got[None, :], oracle.complex_gemv(Ah, xh)[None, :]) <= 1e-5
+    Ai, Aih = _cplx_dev((m, n), 2970, inputs.small_int)
+    xi, xih = _cplx_dev((n,), 2972, inputs.small_int)
+    yi = hs.hs_gemv(Ai, xi, dtype="c32", p=p, K=K)
+    torch.cuda.synchronize()
+    assert np.array_equal(yi.cpu().numpy().astype(np.complex128), oracle.complex_gemv(Aih, xih))
+
+
+def test_complex_gemv_empty_contraction():
+    _skip_no_gpu()
+    A = torch.zeros((5, 0), dtype=torch.complex64, device="cuda")
+    x = torch.zeros((0,), dtype=torch.complex64, device="cuda")
+    y = hs.hs_gemv(A, x, dtype="c32", p=2, K=1)
+    torch.cuda.synchronize()
+    assert torch.equal(y.cpu(), torch.zeros(5, dtype=torch.complex64))
+
+
 def test_complex_strided_views():
     _skip_no_gpu()
     Abig, Ahb = _cplx_dev((100, 150), 980)

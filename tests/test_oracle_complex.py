@@ -107,3 +107,19 @@ def test_backward_embeddings():
     # dB: conj(A)^T as reals times the block embedding of G
     dB_r = oracle.gemm(_as_reals(np.conj(A).T), _blocks(G))
     assert np.array_equal(dB_r, _as_reals(dB))
+
+
+def test_complex_gemv_brute_force_gaussian_integers():
+    """Python's own complex integers, one product at a time (exact)."""
+    A = _cplx((13, 21), 21, inputs.small_int)
+    x = _cplx((21,), 23, inputs.small_int)
+    ref = [sum(complex(A[i, j]) * complex(x[j]) for j in range(21)) for i in range(13)]
+    assert np.array_equal(oracle.complex_gemv(A, x), np.array(ref))
+
+
+def test_complex_gemv_is_a_one_column_product():
+    A = _cplx((30, 47), 25)
+    x = _cplx((47,), 27)
+    got = oracle.complex_gemv(A, x)
+    assert np.allclose(got, oracle.complex_gemm(A, x[:, None])[:, 0], rtol=1e-14, atol=0)
+    assert np.allclose(got, A @ x, rtol=1e-13, atol=1e-13 * np.abs(A) @ np.abs(x))
