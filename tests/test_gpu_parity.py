@@ -155,6 +155,29 @@ def test_precision_config_n8192(dt, K):
     assert e <= TOL[dt]
 
 
+@pytest.mark.parametrize("dt", ["split3_bf16", "f32"])
+def test_headline_step_n8192(dt):
+    """The benchmark's step exactly as bench.py times it: its own inputs
+    (n = 8192, A and B row-scaled, G N(0, 1)), its step function (C = A.B,
+    dA = G.B^T, dB = A^T.G on p = 64, K = 2); C, dA and dB on 16 sampled
+    rows each."""
+    _skip_no_gpu()
+    import bench
+    n, p, K = 8192, 64, 2
+    A, A64 = to_dev(inputs.row_scaled((n, n), seed=inputs.BASE_SEED + 2), dt)
+    B, B64 = to_dev(inputs.row_scaled((n, n), seed=inputs.BASE_SEED + 3), dt)
+    G, G64 = to_dev(inputs.normal((n, n), seed=inputs.BASE_SEED + 4), dt)
+    note("headline step", dt)
+    C, dA, dB = bench.step(hs, A, B, G, dt, p, K)
+    torch.cuda.synchronize()
+    rows = inputs.sample_rows(n, 16, seed=46)
+    e = (err_row(host(C)[rows], oracle.gemm_rows(A64, B64, rows)),
+         err_row(host(dA)[rows], oracle.grad_a_rows(G64, B64, rows)),
+         err_row(host(dB)[rows], oracle.grad_b_rows(A64, G64, rows)))
+    print("headline step %s err_row C %.2e dA %.2e dB %.2e" % ((dt,) + e))
+    assert max(e) <= TOL[dt], e
+
+
 @pytest.mark.parametrize("dt", ["f32", "split3_bf16"])
 def test_backward_config(dt):
     """A 4096 x 2048, B 2048 x 8192, G N(0, 1), p = 16: C, dA, dB on sampled rows."""
@@ -592,6 +615,35 @@ def test_complex_4096_sampled_rows():
         e = err_row(C.cpu().numpy().astype(np.complex128)[rows], ref)
         print("complex n=4096 %s err_row %.3e" % (dt, e))
         assert e <= 1e-5
+
+
+def test_complex_bench_step_n8192():
+    """The complex workload exactly as bench.py times it: n = 8192 complex64
+    N(0, 1) inputs with its seeds, its step (C = A.B, dA = G.B^H,
+    dB = A^H.G on p = 64, K = 2), both forms; 8 sampled rows of each."""
+    _skip_no_gpu()
+    import bench
+    n, p, K = 8192, 64, 2
+    g = inputs.normal
+    A64 = g((n, n), inputs.BASE_SEED + 20) + 1j * g((n, n), inputs.BASE_SEED + 21)
+    B64 = g((n, n), inputs.BASE_SEED + 22) + 1j * g((n, n), inputs.BASE_SEED + 23)
+    G64 = g((n, n), inputs.BASE_SEED + 24) + 1j * g((n, n), inputs.BASE_SEED + 25)
+    A = torch.from_numpy(A64.astype(np.complex64)).cuda()
+    B = torch.from_numpy(B64.astype(np.complex64)).cuda()
+    G = torch.from_numpy(G64.astype(np.complex64)).cuda()
+    Ah, Bh, Gh = (t.cpu().numpy().astype(np.complex128) for t in (A, B, G))
+    del A64, B64, G64
+    rows = inputs.sample_rows(n, 8, seed=47)
+    refs = (oracle.complex_gemm_rows(Ah, Bh, rows),
+            oracle.complex_gemm_rows(Gh, np.conj(Bh).T, rows),
+            oracle.complex_gemm_rows(np.conj(Ah).T, Gh, rows))
+    for dt in CPLX:
+        note("complex bench step", dt)
+        outs = bench.step(hs, A, B, G, dt, p, K)
+        torch.cuda.synchronize()
+        e = tuple(err_row(o.cpu().numpy().astype(np.complex128)[rows], r) for o, r in zip(outs, refs))
+        print("complex step %s err_row C %.2e dA %.2e dB %.2e" % ((dt,) + e))
+        assert max(e) <= 1e-5, (dt, e)
 
 
 CPLX_BW_CASES = [(64, 48, 80, 4, 2), (77, 45, 133, 5, 1), (256, 200, 320, 8, 0), (130, 260, 90, 3, 3)]
