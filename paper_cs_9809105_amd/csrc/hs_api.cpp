@@ -16,6 +16,7 @@
 
 namespace hs {
 hipError_t launch_pack(int kind, int kmajor, const PackArgs &a, hipStream_t st);
+hipError_t launch_pack_mn(int kind, const PackArgs &a, hipStream_t st);
 hipError_t launch_mm(int fam, int form, const MainArgs &a, hipStream_t st);
 hipError_t launch_backshift(int f64, const void *W, int64_t plane, int K, int64_t M, int64_t N,
                             void *Cout, int64_t ldc, hipStream_t st);
@@ -215,6 +216,20 @@ int pack_vec_ok(const Plan &P, const Operand &X) {
     return (X.ld * in % 16 == 0 && aligned(X.ptr, 16) && P.ga.S_k % ue == 0 && P.Kd % ue == 0) ? 1 : 0;
 }
 
+// An MN-major FP32 source goes through pack_mn_kernel (16-byte loads of 4
+// rows, transposed in LDS) when its rows are 16-byte aligned and every
+// 4-row run of a group lies in one stripe.
+bool pack_mn_ok(const Plan &P, const Operand &X, const OperandGeom &g) {
+    if (X.kmajor || X.embed != EMB_NONE) return false;
+    if (P.f.pack != PK_F32 && P.f.pack != PK_SPLIT3 && P.f.pack != PK_FP8) return false;
+    return X.ld % 4 == 0 && aligned(X.ptr, 16) && g.grp_rows % 4 == 0 && (!g.striped || g.S_r % 4 == 0);
+}
+
+hipError_t pack_operand(const Plan &P, const Operand &X, const PackArgs &pa, const OperandGeom &g, hipStream_t st) {
+    if (pack_mn_ok(P, X, g)) return launch_pack_mn(P.f.pack, pa, st);
+    return launch_pack(P.f.pack, X.kmajor, pa, st);
+}
+
 // One product through the hyper-systolic path.  The plan must come from
 // make_plan with the same sizes; ws holds at least plan.total bytes.
 hs_status run_product(const Plan &P, const Operand &X, const Operand &Y, void *out, int64_t ldo,
@@ -239,7 +254,7 @@ hs_status run_product(const Plan &P, const Operand &X, const Operand &Y, void *o
     pa.vec = pack_vec_ok(P, X);
     pa.exps = ea; pa.exp_tiles_k = P.tiles_k; pa.refine = P.f.form;
     pa.embed = X.embed;
-    hipError_t e = launch_pack(P.f.pack, X.kmajor, pa, stream);
+    hipError_t e = pack_operand(P, X, pa, P.ga, stream);
     if (e != hipSuccess) return HS_ERR_LAUNCH_FAILED;
     PackArgs pb{};
     pb.src = Y.ptr; pb.ld = Y.ld; pb.g = P.gb; pb.dst = w + P.off_b;
@@ -247,7 +262,7 @@ hs_status run_product(const Plan &P, const Operand &X, const Operand &Y, void *o
     pb.vec = pack_vec_ok(P, Y);
     pb.exps = eb; pb.exp_tiles_k = P.tiles_k; pb.refine = P.f.form;
     pb.embed = Y.embed;
-    e = launch_pack(P.f.pack, Y.kmajor, pb, stream);
+    e = pack_operand(P, Y, pb, P.gb, stream);
     if (e != hipSuccess) return HS_ERR_LAUNCH_FAILED;
 
     MainArgs m{};

@@ -6,6 +6,8 @@
 //   pack_kernel      operand preparation: copies (or splits, or quantises) a
 //                    row-major operand into the packed tile layout described
 //                    in hs_internal.h; HBM bound.
+//   pack_mn_kernel   the same for an MN-major FP32 source, read as 16-byte
+//                    runs of 4 rows and transposed through LDS.
 //   mm_kernel        the hot loop: one workgroup is virtual processor v for
 //                    one (stripe sub-group, column tile).  For step j it
 //                    fetches block kb = (v + jK) mod p of the travelling
@@ -19,7 +21,7 @@
 //                    FP64, fixed order.
 //   gemv_kernel      y = A x with the same index map, collector form: one
 //                    wave owns a row and combines the K partial dot products
-//                    in the back-shift order.
+//                    in the back-shift order (gemv_c32_kernel: complex64).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -146,6 +148,185 @@ template <> struct PackTraits<PK_B16> { typedef uint16_t S; static const int UE 
 template <> struct PackTraits<PK_SPLIT3> { typedef float S; static const int UE = 8; static const int ESZ = 2; static const int NP = 3; };
 template <> struct PackTraits<PK_FP8> { typedef float S; static const int UE = 16; static const int ESZ = 1; static const int NP = 2; };
 
+// Write one 16-byte unit (of each piece) of the packed image: row rr of
+// group grp, block kb, chunk ch, plane half, from the unit's values.
+template <int KIND>
+DEVI void pack_emit(const PackArgs &a, uint32_t grp, uint32_t kb, uint32_t ch, uint32_t half, uint32_t rr,
+                    int64_t row, bool rvalid, int64_t kk0, const float *vals_f, const double *vals_d,
+                    const uint16_t *vals_h) {
+    const OperandGeom &g = a.g;
+    const uint32_t nch = (uint32_t)g.nch, gr = (uint32_t)g.grp_rows;
+    // chunk = UPR planes of 16 bytes per row: [plane][row][16 bytes]
+    // [group][piece][block][chunk][plane][row][16 bytes]; a striped group's
+    // position is shifted by the `wrap` copies ahead of stripe 0, and a group
+    // of the last `wrap` stripes is written a second time as its copy
+    const int64_t inner = ((int64_t)kb * nch + ch) * gr * g.chunk_bytes + ((int64_t)half * gr + rr) * 16;
+    const int64_t gpos = g.striped ? (int64_t)grp + (int64_t)g.wrap * g.GS : (int64_t)grp;
+    uint8_t *dst = (uint8_t *)a.dst + gpos * g.group_bytes + inner;
+    uint8_t *dst2 = nullptr;
+    if (g.striped && g.wrap > 0) {
+        const int64_t stripe = grp / g.GS;
+        if (stripe >= g.p - g.wrap)
+            dst2 = (uint8_t *)a.dst + ((stripe - g.p + g.wrap) * g.GS + grp % g.GS) * g.group_bytes + inner;
+    }
+    auto put = [&](int64_t at, const u32x4 &w) {
+        *(u32x4 *)(dst + at) = w;
+        if (dst2) *(u32x4 *)(dst2 + at) = w;
+    };
+    if constexpr (KIND == PK_F64) {
+        put(0, __builtin_bit_cast(u32x4, make_double2(vals_d[0], vals_d[1])));
+    } else if constexpr (KIND == PK_F32) {
+        put(0, u32x4{__float_as_uint(vals_f[0]), __float_as_uint(vals_f[1]), __float_as_uint(vals_f[2]),
+                     __float_as_uint(vals_f[3])});
+    } else if constexpr (KIND == PK_B16) {
+        u32x4 w;
+        w[0] = vals_h[0] | ((uint32_t)vals_h[1] << 16);
+        w[1] = vals_h[2] | ((uint32_t)vals_h[3] << 16);
+        w[2] = vals_h[4] | ((uint32_t)vals_h[5] << 16);
+        w[3] = vals_h[6] | ((uint32_t)vals_h[7] << 16);
+        put(0, w);
+    } else if constexpr (KIND == PK_FP8) {
+        // all 16 elements of the unit lie in one 128 x 128 scale tile
+        int e = 0, e1 = 0;
+        if (rvalid && kk0 < g.Kd) {
+            const int64_t t2 = ((row / FP8_TILE) * a.exp_tiles_k + kk0 / FP8_TILE) * 2;
+            e = a.exps[t2];
+            e1 = a.exps[t2 + 1];
+        }
+        u32x4 w0 = {0, 0, 0, 0}, w1 = {0, 0, 0, 0};
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const float xs = ldexpf(vals_f[i], e);             // exact
+            const uint32_t q0 = f32_to_e4m3_rne(xs);
+            w0[i / 4] |= q0 << ((i % 4) * 8);
+            if (a.refine) {
+                const uint32_t q1 = f32_to_e4m3_rne(ldexpf(xs - e4m3_to_f32(q0), e1));
+                w1[i / 4] |= q1 << ((i % 4) * 8);
+            }
+        }
+        put(0, w0);
+        if (a.refine) put(g.piece_bytes, w1);
+    } else {   // PK_SPLIT3: a0 = bf16(a), a1 = bf16(a - a0), a2 = bf16(a - a0 - a1)
+        uint16_t p0[8], p1[8], p2[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const float x = vals_f[e];
+            p0[e] = f32_to_bf16_rne(x);
+            const float r1 = x - bf16_to_f32(p0[e]);      // exact in fp32
+            p1[e] = f32_to_bf16_rne(r1);
+            const float r2 = r1 - bf16_to_f32(p1[e]);     // exact in fp32
+            p2[e] = f32_to_bf16_rne(r2);
+        }
+        uint16_t *pc[3] = {p0, p1, p2};
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const uint16_t *h = pc[q];
+            u32x4 w;
+            w[0] = h[0] | ((uint32_t)h[1] << 16);
+            w[1] = h[2] | ((uint32_t)h[3] << 16);
+            w[2] = h[4] | ((uint32_t)h[5] << 16);
+            w[3] = h[6] | ((uint32_t)h[7] << 16);
+            put(q * g.piece_bytes, w);
+        }
+    }
+}
+
+// An MN-major unit of pack_kernel's numbering: row rr of group grp, block
+// kb, chunk ch, plane half, and where its elements lie in the source.
+struct MnUnit {
+    uint32_t rr, half, ch, kb, grp;
+    int64_t row, kin0, kk0;
+    bool rvalid;
+};
+
+template <int KIND>
+DEVI MnUnit mn_decode(uint32_t u, const OperandGeom &g) {
+    typedef PackTraits<KIND> T;
+    const int KC = g.chunk_bytes / T::ESZ;
+    const uint32_t UPR = (uint32_t)(g.chunk_bytes / 16), nch = (uint32_t)g.nch, p = (uint32_t)g.p;
+    const uint32_t gr = (uint32_t)g.grp_rows;
+    MnUnit d;
+    uint32_t t = u;
+    d.rr = t % gr;    t /= gr;
+    d.half = t % UPR; t /= UPR;
+    d.ch = t % nch;   t /= nch;
+    d.kb = t % p;
+    d.grp = t / p;
+    if (g.striped) {
+        const int64_t stripe = d.grp / g.GS, msub = d.grp % g.GS;
+        const int64_t within = msub * gr + d.rr;
+        d.row = stripe * g.S_r + within;
+        d.rvalid = within < g.S_r && d.row < g.R;
+    } else {
+        d.row = (int64_t)d.grp * gr + d.rr;
+        d.rvalid = d.row < g.R;
+    }
+    d.kin0 = (int64_t)d.ch * KC + d.half * T::UE;
+    d.kk0 = (int64_t)d.kb * g.S_k + d.kin0;
+    return d;
+}
+
+// MN-major FP32 source (copy, split and FP8 kinds), transposed through LDS:
+// the workgroup's 256 units (pack_kernel's numbering: rows fastest) are read
+// as 16-byte runs of 4 rows per contraction index -- 64 lanes read 64 runs,
+// one contiguous stretch per group -- into an [element][unit] tile, then each
+// thread packs and writes its own unit as pack_kernel does, so consecutive
+// threads still write consecutive 16-byte rows.  Host: ld % 4 == 0, source
+// 16-byte aligned, grp_rows % 4 == 0, S_r % 4 == 0 for a striped operand;
+// total_units is a multiple of 4.
+template <int KIND>
+__global__ __launch_bounds__(256) void pack_mn_kernel(PackArgs a) {
+    typedef PackTraits<KIND> T;
+    constexpr int UE = T::UE;                   // 4, 8 or 16 elements per unit
+    __shared__ float tile[UE][256];
+    const OperandGeom &g = a.g;
+    const float *src = (const float *)a.src;
+    const uint32_t base = blockIdx.x * 256u;    // host: total_units < 2^31
+#pragma unroll
+    for (int i = 0; i < UE / 4; ++i) {
+        const uint32_t q = threadIdx.x + 256u * i;
+        const uint32_t quad = q % 64, e = q / 64;
+        const uint32_t u = base + quad * 4;     // units u .. u+3: rows rr .. rr+3 of one group
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (u < (uint32_t)a.total_units) {
+            const MnUnit d = mn_decode<KIND>(u, g);
+            const int64_t kk = d.kk0 + e;
+            if (d.kin0 + e < g.S_k && kk < g.Kd) {
+                bool rv[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    if (g.striped) {
+                        const int64_t within = (int64_t)(d.grp % g.GS) * g.grp_rows + d.rr + r;
+                        rv[r] = within < g.S_r && d.row + r < g.R;
+                    } else {
+                        rv[r] = d.row + r < g.R;
+                    }
+                }
+                const float *q4 = src + kk * a.ld + d.row;
+                if (rv[0] && rv[1] && rv[2] && rv[3]) {
+                    v = *(const float4 *)q4;
+                } else {
+                    v.x = rv[0] ? q4[0] : 0.f;
+                    v.y = rv[1] ? q4[1] : 0.f;
+                    v.z = rv[2] ? q4[2] : 0.f;
+                    v.w = rv[3] ? q4[3] : 0.f;
+                }
+            }
+        }
+        *(float4 *)&tile[e][quad * 4] = v;
+    }
+    __syncthreads();
+    const uint32_t u = base + threadIdx.x;
+    if (u >= (uint32_t)a.total_units) return;
+    const MnUnit d = mn_decode<KIND>(u, g);
+    float vals_f[UE];
+    double vals_d[1] = {0.0};
+    uint16_t vals_h[1] = {0};
+#pragma unroll
+    for (int e = 0; e < UE; ++e) vals_f[e] = tile[e][threadIdx.x];
+    pack_emit<KIND>(a, d.grp, d.kb, d.ch, d.half, d.rr, d.row, d.rvalid, d.kk0, vals_f, vals_d, vals_h);
+}
+
 // One thread makes one 16-byte unit of the packed image (for the split form,
 // the same unit of each of the three pieces).  Consecutive threads take
 // consecutive rows of one (group, block, chunk, plane), so the packed writes
@@ -253,79 +434,7 @@ __global__ __launch_bounds__(256) void pack_kernel(PackArgs a) {
             else vals_f[e] = ok ? (neg ? -(float)src[idx] : (float)src[idx]) : 0.0f;
         }
     }
-    // chunk = UPR planes of 16 bytes per row: [plane][row][16 bytes]
-    // [group][piece][block][chunk][plane][row][16 bytes]; a striped group's
-    // position is shifted by the `wrap` copies ahead of stripe 0, and a group
-    // of the last `wrap` stripes is written a second time as its copy
-    const int64_t inner = ((int64_t)kb * nch + ch) * gr * g.chunk_bytes + ((int64_t)half * gr + rr) * 16;
-    const int64_t gpos = g.striped ? (int64_t)grp + (int64_t)g.wrap * g.GS : (int64_t)grp;
-    uint8_t *dst = (uint8_t *)a.dst + gpos * g.group_bytes + inner;
-    uint8_t *dst2 = nullptr;
-    if (g.striped && g.wrap > 0) {
-        const int64_t stripe = grp / g.GS;
-        if (stripe >= g.p - g.wrap)
-            dst2 = (uint8_t *)a.dst + ((stripe - g.p + g.wrap) * g.GS + grp % g.GS) * g.group_bytes + inner;
-    }
-    auto put = [&](int64_t at, const u32x4 &w) {
-        *(u32x4 *)(dst + at) = w;
-        if (dst2) *(u32x4 *)(dst2 + at) = w;
-    };
-    if constexpr (KIND == PK_F64) {
-        put(0, __builtin_bit_cast(u32x4, make_double2(vals_d[0], vals_d[1])));
-    } else if constexpr (KIND == PK_F32) {
-        put(0, u32x4{__float_as_uint(vals_f[0]), __float_as_uint(vals_f[1]), __float_as_uint(vals_f[2]),
-                     __float_as_uint(vals_f[3])});
-    } else if constexpr (KIND == PK_B16) {
-        u32x4 w;
-        w[0] = vals_h[0] | ((uint32_t)vals_h[1] << 16);
-        w[1] = vals_h[2] | ((uint32_t)vals_h[3] << 16);
-        w[2] = vals_h[4] | ((uint32_t)vals_h[5] << 16);
-        w[3] = vals_h[6] | ((uint32_t)vals_h[7] << 16);
-        put(0, w);
-    } else if constexpr (KIND == PK_FP8) {
-        // all 16 elements of the unit lie in one 128 x 128 scale tile
-        int e = 0, e1 = 0;
-        if (rvalid && kk0 < g.Kd) {
-            const int64_t t2 = ((row / FP8_TILE) * a.exp_tiles_k + kk0 / FP8_TILE) * 2;
-            e = a.exps[t2];
-            e1 = a.exps[t2 + 1];
-        }
-        u32x4 w0 = {0, 0, 0, 0}, w1 = {0, 0, 0, 0};
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const float xs = ldexpf(vals_f[i], e);             // exact
-            const uint32_t q0 = f32_to_e4m3_rne(xs);
-            w0[i / 4] |= q0 << ((i % 4) * 8);
-            if (a.refine) {
-                const uint32_t q1 = f32_to_e4m3_rne(ldexpf(xs - e4m3_to_f32(q0), e1));
-                w1[i / 4] |= q1 << ((i % 4) * 8);
-            }
-        }
-        put(0, w0);
-        if (a.refine) put(g.piece_bytes, w1);
-    } else {   // PK_SPLIT3: a0 = bf16(a), a1 = bf16(a - a0), a2 = bf16(a - a0 - a1)
-        uint16_t p0[8], p1[8], p2[8];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const float x = vals_f[e];
-            p0[e] = f32_to_bf16_rne(x);
-            const float r1 = x - bf16_to_f32(p0[e]);      // exact in fp32
-            p1[e] = f32_to_bf16_rne(r1);
-            const float r2 = r1 - bf16_to_f32(p1[e]);     // exact in fp32
-            p2[e] = f32_to_bf16_rne(r2);
-        }
-        uint16_t *pc[3] = {p0, p1, p2};
-#pragma unroll
-        for (int q = 0; q < 3; ++q) {
-            const uint16_t *h = pc[q];
-            u32x4 w;
-            w[0] = h[0] | ((uint32_t)h[1] << 16);
-            w[1] = h[2] | ((uint32_t)h[3] << 16);
-            w[2] = h[4] | ((uint32_t)h[5] << 16);
-            w[3] = h[6] | ((uint32_t)h[7] << 16);
-            put(q * g.piece_bytes, w);
-        }
-    }
+    pack_emit<KIND>(a, grp, kb, ch, half, rr, row, rvalid, kk0, vals_f, vals_d, vals_h);
 }
 
 // ---------------------------------------------------------------------------
@@ -1144,6 +1253,18 @@ hipError_t launch_mm(int fam, int form, const MainArgs &a, hipStream_t st) {
     if (fam == FAM_FP8 && form == 0) return launch_mm_t<FAM_FP8, 0, 256, 256, 2, HS_WAVES_FP8>(a, st);
     if (fam == FAM_FP8 && form == 1) return launch_mm_t<FAM_FP8, 1, 256, 256, 1, HS_WAVES_FP8R>(a, st);
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_pack_mn(int kind, const PackArgs &a, hipStream_t st) {
+    if (a.total_units == 0) return hipSuccess;
+    const unsigned nb = nblocks(a.total_units);
+    switch (kind) {
+        case PK_F32: hipLaunchKernelGGL((pack_mn_kernel<PK_F32>), dim3(nb), dim3(256), 0, st, a); break;
+        case PK_SPLIT3: hipLaunchKernelGGL((pack_mn_kernel<PK_SPLIT3>), dim3(nb), dim3(256), 0, st, a); break;
+        case PK_FP8: hipLaunchKernelGGL((pack_mn_kernel<PK_FP8>), dim3(nb), dim3(256), 0, st, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_fp8_exps(const Fp8ExpArgs &a, int64_t tiles, hipStream_t st) {
