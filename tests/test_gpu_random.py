@@ -1,0 +1,172 @@
+"""Seeded random-shape parity sweep of every entry point against the FP64
+oracle (GPU).
+
+Each case draws sizes, a schedule (p, K | p) and a dtype from a fixed seed,
+so a failure names a reproducible case.  Shapes a form does not take (the
+FP8 forms need whole 64-element contraction blocks) are recognised by
+hs_workspace_size returning SIZE_MAX and skipped.  Tolerances are those of
+tests/test_gpu_parity.py (err_row) and tests/test_gpu_nbody.py; outputs
+are NaN-poisoned, and small-integer cases must match bit for bit.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle.metrics import err_row
+from paper_cs_9809105_amd import binding as B
+from paper_cs_9809105_amd import inputs
+from tests._gpu import gpu_available, host, note, poisoned, to_dev
+
+pytestmark = pytest.mark.gpu
+
+if gpu_available():
+    import torch
+    import paper_cs_9809105_amd as hs
+
+TOL = {"f64": 1e-12, "f32": 1e-5, "split3_bf16": 1e-5, "bf16": 1.5e-2, "f16": 3e-3,
+       "fp8_e4m3": 1e-1, "fp8_e4m3_r1": 1e-2}
+DTYPES = list(TOL)
+
+
+def _skip_no_gpu():
+    if not gpu_available():
+        pytest.skip("no GPU")
+
+
+def _schedule(g, max_p=24):
+    p = int(g.integers(1, max_p + 1))
+    divs = [d for d in range(1, p + 1) if p % d == 0]
+    return p, int(divs[int(g.integers(0, len(divs)))])
+
+
+def _case(seed):
+    g = inputs.rng(31000 + seed)
+    m, n, k = (int(x) for x in g.integers(1, 400, size=3))
+    p, K = _schedule(g)
+    dt = DTYPES[int(g.integers(0, len(DTYPES)))]
+    ints = bool(g.integers(0, 4) == 0)
+    return g, m, n, k, p, K, dt, ints
+
+
+def _out_dtype(dt):
+    return torch.float64 if dt == "f64" else torch.float32
+
+
+@pytest.mark.parametrize("seed", range(48))
+def test_random_products(seed):
+    """C = A.B, C = A^T.B and the backward pair on one random case."""
+    _skip_no_gpu()
+    g, m, n, k, p, K, dt, ints = _case(seed)
+
+    def taken(m, n, k, p, K):
+        return all(B.hs_workspace_size(op, a, b, c, dt, p, K) != B.SIZE_MAX
+                   for op, a, b, c in ((B.HS_OP_GEMM, m, n, k), (B.HS_OP_GEMM_TN, m, n, k),
+                                       (B.HS_OP_GEMM, m, k, n), (B.HS_OP_GEMM, k, n, m)))
+    tries = 0
+    while dt.startswith("fp8") and not taken(m, n, k, p, K) and tries < 50:
+        # the FP8 forms take whole 32-row stripe groups and 64-element
+        # contraction chunks: draw from that family
+        p = int(g.choice([1, 2, 4, 8]))
+        K = int(g.choice([d for d in (1, 2, 4, 8) if p % d == 0]))
+        m, n, k = (p * 64 * int(g.integers(1, 4)) for _ in range(3))
+        tries += 1
+    if not taken(m, n, k, p, K):
+        pytest.skip("shape not taken by %s" % dt)
+    gen = (lambda s, sd: inputs.small_int(s, sd, -4, 4)) if ints else (lambda s, sd: inputs.uniform(s, sd))
+    A, A64 = to_dev(gen((m, k), 32000 + seed), dt)
+    At, At64 = to_dev(np.ascontiguousarray(A64.T), dt)
+    Bm, B64 = to_dev(gen((k, n), 33000 + seed), dt)
+    G, G64 = to_dev(gen((m, n), 34000 + seed), dt)
+    note("random product", seed, dt, (m, n, k), (p, K), "ints" if ints else "")
+    C = hs.hs_gemm(A, Bm, dtype=dt, p=p, K=K, out=poisoned((m, n), _out_dtype(dt)))
+    Ct = hs.hs_gemm_tn(At, Bm, dtype=dt, p=p, K=K, out=poisoned((m, n), _out_dtype(dt)))
+    dA, dB = hs.hs_gemm_backward(A, Bm, G, dtype=dt, p=p, K=K)
+    torch.cuda.synchronize()
+    ref = oracle.gemm(A64, B64)
+    rA, rB = oracle.backward(A64, B64, G64)
+    got = [host(C), host(Ct), host(dA), host(dB)]
+    for x in got:
+        assert not np.isnan(x).any()
+    if ints:   # |x| <= 4: exact in every form and every partial sum is exact
+        assert np.array_equal(got[0], ref) and np.array_equal(got[1], ref)
+        assert np.array_equal(got[2], rA) and np.array_equal(got[3], rB)
+    else:
+        e = (err_row(got[0], ref), err_row(got[1], ref), err_row(got[2], rA), err_row(got[3], rB))
+        assert max(e) <= TOL[dt], (seed, dt, e)
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_random_gemv(seed):
+    _skip_no_gpu()
+    g = inputs.rng(35000 + seed)
+    m, n = (int(x) for x in g.integers(1, 3000, size=2))
+    p, K = _schedule(g, 64)
+    dt = ["f32", "f64"][seed % 2]
+    A, A64 = to_dev(inputs.normal((m, n), 36000 + seed), dt)
+    x, x64 = to_dev(inputs.normal((n,), 37000 + seed), dt)
+    note("random gemv", seed, dt, (m, n), (p, K))
+    y = hs.hs_gemv(A, x, dtype=dt, p=p, K=K)
+    torch.cuda.synchronize()
+    tol = 1e-12 if dt == "f64" else 1e-5
+    assert err_row(host(y)[None, :], oracle.gemv(A64, x64)[None, :]) <= tol
+
+
+def _cplx(shape, seed):
+    z = inputs.normal(shape, seed) + 1j * inputs.normal(shape, seed + 1)
+    t = torch.from_numpy(np.ascontiguousarray(z.astype(np.complex64)))
+    return t.cuda(), t.numpy().astype(np.complex128)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_complex(seed):
+    """Complex C = A.B, A^T.B, the backward pair and y = A.x on one random case."""
+    _skip_no_gpu()
+    g = inputs.rng(38000 + seed)
+    m, n, k = (int(x) for x in g.integers(1, 300, size=3))
+    p, K = _schedule(g)
+    dt = ["c32", "c32_split3_bf16"][seed % 2]
+    A, Ah = _cplx((m, k), 39000 + seed)
+    At, Ath = _cplx((k, m), 40000 + seed)
+    Bm, Bh = _cplx((k, n), 41000 + seed)
+    G, Gh = _cplx((m, n), 42000 + seed)
+    x, xh = _cplx((k,), 43000 + seed)
+    note("random complex", seed, dt, (m, n, k), (p, K))
+    C = hs.hs_gemm(A, Bm, dtype=dt, p=p, K=K)
+    Ct = hs.hs_gemm_tn(At, Bm, dtype=dt, p=p, K=K)
+    dA, dB = hs.hs_gemm_backward(A, Bm, G, dtype=dt, p=p, K=K)
+    y = hs.hs_gemv(A, x, dtype="c32", p=p, K=K)
+    torch.cuda.synchronize()
+
+    def c(t):
+        return t.cpu().numpy().astype(np.complex128)
+    e = (err_row(c(C), oracle.complex_gemm(Ah, Bh)),
+         err_row(c(Ct), oracle.complex_gemm(Ath.T, Bh)),
+         err_row(c(dA), oracle.complex_gemm(Gh, np.conj(Bh).T)),
+         err_row(c(dB), oracle.complex_gemm(np.conj(Ah).T, Gh)),
+         err_row(c(y)[None, :], oracle.complex_gemv(Ah, xh)[None, :]))
+    assert max(e) <= 1e-5, (seed, dt, e)
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_random_nbody(seed):
+    _skip_no_gpu()
+    g = inputs.rng(44000 + seed)
+    n = int(g.integers(1, 3000))
+    p, K = _schedule(g, 64)
+    dt = ["f32", "f64"][seed % 2]
+    eps2 = [0.0, 1e-4, 1e-2][seed % 3]
+    X = inputs.plummer(n, 45000 + seed, unequal=True)
+    t = torch.from_numpy(X).to(torch.float32 if dt == "f32" else torch.float64)
+    X64 = t.double().numpy()
+    e2 = float(np.float32(eps2)) if dt == "f32" else eps2
+    note("random nbody", seed, dt, n, (p, K), eps2)
+    out = poisoned((n, 4), t.dtype)
+    hs.hs_nbody(t.cuda(), e2, dtype=dt, p=p, K=K, out=out)
+    torch.cuda.synchronize()
+    got = host(out)
+    ref, scale = oracle.nbody(X64, e2, with_scale=True)
+    u = 2.0 ** -24 if dt == "f32" else 2.0 ** -53
+    ea = (np.abs(got[:, :3] - ref[:, :3]).max(axis=1) / np.where(scale > 0, scale, 1.0)).max(initial=0.0)
+    ep = (np.abs(got[:, 3] - ref[:, 3]) / np.where(ref[:, 3] != 0, np.abs(ref[:, 3]), 1.0)).max(initial=0.0)
+    assert np.isfinite(got).all()
+    assert ea <= (n / K + 20) * u and ep <= (n / K + 8) * u, (seed, ea, ep)
