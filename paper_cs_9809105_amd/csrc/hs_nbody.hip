@@ -89,15 +89,16 @@ DEVI void travel(const T *__restrict__ src, const int cnt, const int i, const T 
 #pragma unroll
         for (int u = 0; u < UB; ++u) {
 #pragma unroll
-            for (int c = 0; c < 4; ++c) z[u][c] = src[(jj + u) * 4 + c];
+            for (int c = 0; c < 4; ++c) z[u][c] = src[(int64_t)(jj + u) * 4 + c];
         }
 #pragma unroll
         for (int u = 0; u < UB; ++u)
             interact<T, KR, SELF>(z[u][0], z[u][1], z[u][2], z[u][3], jj + u, i, eps2, px, py, pz, ax, ay, az, ph);
     }
-    for (; jj < cnt; ++jj)
-        interact<T, KR, SELF>(src[jj * 4], src[jj * 4 + 1], src[jj * 4 + 2], src[jj * 4 + 3], jj, i, eps2, px, py,
-                              pz, ax, ay, az, ph);
+    for (; jj < cnt; ++jj) {
+        const T *z = src + (int64_t)jj * 4;
+        interact<T, KR, SELF>(z[0], z[1], z[2], z[3], jj, i, eps2, px, py, pz, ax, ay, az, ph);
+    }
 }
 
 // Grid: p * sub * tgroups workgroups of 256 threads (host-checked).
