@@ -107,7 +107,8 @@ typedef enum {
     HS_OK = 0,
     HS_ERR_INVALID_VALUE = 1,       /* bad shape, ld, pointer, schedule */
     HS_ERR_NOT_SUPPORTED = 2,       /* dtype not available for this call, or a
-                                       size the kernels cannot address (one
+                                       size the kernels cannot address (a
+                                       dimension of 2^31 or more, or one
                                        workgroup's packed region above 4 GiB) */
     HS_ERR_WORKSPACE_TOO_SMALL = 3, /* ws_bytes < hs_workspace_size(...) */
     HS_ERR_LAUNCH_FAILED = 4        /* the HIP runtime rejected a launch */

@@ -106,6 +106,10 @@ hs_status make_plan(int64_t M, int64_t N, int64_t Kd, hs_dtype dt, hs_schedule s
     hs_status st = hs_schedule_resolve(s, &r);
     if (st != HS_OK) return st;
     if (M < 0 || N < 0 || Kd < 0) return HS_ERR_INVALID_VALUE;
+    // every dimension below 2^31 keeps the products of two of them, and so
+    // every count and byte size below, inside 64 bits
+    const int64_t kMaxDim = std::numeric_limits<int32_t>::max();
+    if (M > kMaxDim || N > kMaxDim || Kd > kMaxDim) return HS_ERR_NOT_SUPPORTED;
     P->p = r.p; P->K = r.K; P->Kt = r.p / r.K;
     P->M = M; P->N = N; P->Kd = Kd;
     const int BMT = mm_tile_rows(P->f.fam), BNT = mm_tile_cols(P->f.fam);
@@ -533,6 +537,7 @@ hs_status hs_gemv(int64_t m, int64_t n, hs_dtype dtype, hs_schedule s,
     HS_TRY(hs_schedule_resolve(s, &r));
     const int cplx = dtype == HS_C32;
     const size_t esz = dtype == HS_F32 ? 4 : 8;
+    if (m > std::numeric_limits<int32_t>::max()) return HS_ERR_NOT_SUPPORTED;   // 4 rows per workgroup, 32-bit grid
     HS_TRY(check_mat(A, m, n, lda, esz));
     if (n > 0 && m > 0 && (!x || !aligned(x, esz))) return HS_ERR_INVALID_VALUE;
     if (m > 0 && (!y || !aligned(y, esz))) return HS_ERR_INVALID_VALUE;

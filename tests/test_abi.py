@@ -346,3 +346,20 @@ def test_nbody_rejects_bad_arguments():
     assert _nbody(10, nb=2 * 10 * 16 - 1) == B.HS_ERR_WORKSPACE_TOO_SMALL
     assert _nbody(10, ws=FAKE + (1 << 33) + 64) == E               # workspace alignment
     assert _nbody(1 << 31, ws=None, nb=0, K=1) == B.HS_ERR_NOT_SUPPORTED
+
+
+def test_dimensions_of_2_31_or_more_are_not_supported():
+    """Each dimension must stay below 2^31 (products of two then fit in 64
+    bits); above, every call is rejected before any launch."""
+    ws = B.hs_workspace_size
+    big = 1 << 31
+    for op in (B.HS_OP_GEMM, B.HS_OP_GEMM_TN, B.HS_OP_BACKWARD):
+        assert ws(op, big, 8, 8, "f32", 4, 2) == B.SIZE_MAX
+        assert ws(op, 8, big, 8, "f32", 4, 2) == B.SIZE_MAX
+        assert ws(op, 8, 8, big, "f32", 4, 2) == B.SIZE_MAX
+        assert ws(op, 1 << 40, 1 << 40, 1 << 30, "f32", 1, 1) == B.SIZE_MAX
+    assert ws(B.HS_OP_GEMM, 8, 1 << 30, 8, "c32", 4, 2) == B.SIZE_MAX     # 2n reals
+    assert _gemm(m=big, n=8, k=8, lda=8, ldb=8, ldc=8) == B.HS_ERR_NOT_SUPPORTED
+    L = B.lib()
+    assert L.hs_gemv(big, 8, B.HS_F32, B.hs_schedule(4, 2), FAKE, 8, FAKE, FAKE, None, 0, None) == \
+        B.HS_ERR_NOT_SUPPORTED
