@@ -31,7 +31,8 @@ def ordered_partial_sums(base):
 
 
 def h_range_complete(A, B, n):
-    """True iff every m in 0..n-1 is a sum of two ordered partial sums (Def. DEF:OPTI2)."""
+    """True iff every m in 0..n-1 is a sum of two ordered partial sums (Def. DEF:OPTI2,
+    read literally: any contiguous run of each base)."""
     sa, sb = ordered_partial_sums(A), ordered_partial_sums(B)
     reach = {x + y for x in sa for y in sb}
     return all(m in reach for m in range(n))
@@ -45,3 +46,22 @@ def shifts_two_array(K, Kt):
 def shifts_matrix_product(K, Kt):
     """Thm. GAIN3, Eq. COMPL: 1 pre-shift of B, K~-1 shifts of A, K-1 of C."""
     return K + Kt - 1
+
+
+def prefix_sums(base):
+    """Positions an array visits when moved by the strides of ``base`` in turn
+    (a_0 = 0 first): 0, a_1, a_1 + a_2, ..."""
+    out, acc = [], 0
+    for a in base:
+        acc += a
+        out.append(acc)
+    return out
+
+
+def recipe_complete(A, B, n):
+    """True iff the two-array recipe (Sec. 4.1) with these bases pairs every
+    offset: replica t of x sits at offset P_A(t), the travelling z at P_B(j),
+    so the pairs met have offsets (P_B(j) - P_A(t)) mod n, and all n residues
+    must occur."""
+    pa, pb = prefix_sums(A), prefix_sums(B)
+    return len({(y - x) % n for x in pa for y in pb}) == n

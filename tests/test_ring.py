@@ -183,6 +183,49 @@ def test_min_length_at_sqrt():
         assert best == r
 
 
+def _shortest_complete(n, complete, max_len):
+    """Smallest k + k' over all base pairs with strides 1..n-1 that
+    ``complete`` accepts (None if none up to max_len)."""
+    import itertools
+    for L in range(0, max_len + 1):
+        for k in range(L + 1):
+            for sa in itertools.product(range(1, n), repeat=k):
+                for sb in itertools.product(range(1, n), repeat=L - k):
+                    if complete([0] + list(sa), [0] + list(sb), n):
+                        return L
+    return None
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 5, 6, 8, 9, 10, 12])
+def test_two_array_minimum_length_brute_force(n):
+    """Thm. MINIMUM2 by exhaustive search: over every pair of bases with
+    strides 1..n-1, the shortest pair the recipe makes complete has k + k'
+    equal to the best regular pair's (K - 1) + (n/K - 1), and at least the
+    bound 2 (sqrt(n) - 1) ((k + 1)(k' + 1) offsets must cover n)."""
+    best_regular = min((K - 1) + (n // K - 1) for K in _divisors(n))
+    for K in _divisors(n):
+        assert bases.recipe_complete(*bases.regular_bases_two_array(n, K), n)
+    shortest = _shortest_complete(n, bases.recipe_complete, best_regular)
+    assert shortest is not None and shortest >= 2 * (n ** 0.5 - 1) - 1e-12
+    # the regular pairs are shortest except where a non-divisor split of n
+    # into (k + 1)(k' + 1) >= n offsets is shorter (n = 5, 10: prime factors)
+    assert shortest == min(k + kp for k in range(n) for kp in range(n) if (k + 1) * (kp + 1) >= n)
+
+
+def test_literal_definition_admits_pairs_the_recipe_cannot_realise():
+    """Def. DEF:OPTI2 read literally (any contiguous runs of both bases)
+    accepts A = (0, 1), B = (0, 2, 4) for n = 8: k + k' = 3, below the bound
+    2 (sqrt(8) - 1) = 3.66 of Thm. MINIMUM2.  The recipe meets only the
+    offsets P_B(j) - P_A(t) mod 8 with P_A = {0, 1}, P_B = {0, 2, 6}, i.e.
+    {0, 1, 2, 5, 6, 7}, never 3 or 4, so it is not complete; read as the
+    recipe runs, the bound holds."""
+    A, Bb = [0, 1], [0, 2, 4]
+    assert bases.h_range_complete(A, Bb, 8)
+    assert not bases.recipe_complete(A, Bb, 8)
+    assert _shortest_complete(8, bases.h_range_complete, 4) == 3 < 2 * (8 ** 0.5 - 1)
+    assert _shortest_complete(8, bases.recipe_complete, 4) == 4
+
+
 def test_gain_factors():
     """Thm. GAIN3: R = (p-1)/(K+K~-1) ~ sqrt(p)/2;  Thm. GAIN2: T = 2K+K~-3."""
     for p in (16, 64, 256, 1024):
