@@ -72,7 +72,8 @@ def _run(Xd, eps2, dt, p, K):
 
 # (n, p, K): several workgroups per block, ragged last block, blocks left
 # empty (n < p S), K = 1 (systolic), K = p, prime p, K with 2, 3 and 4 replica
-# groups per position, more than one workgroup slice per block.
+# groups per position, the largest ring (p = 4096, 32 replica groups, blocks
+# of 2 bodies), and two workgroup slices per block (70000 bodies, p = 256).
 CASES = [
     (4096, 16, 4),
     (4096, 16, 1),
@@ -87,6 +88,8 @@ CASES = [
     (5, 4, 2),
     (2, 2, 2),
     (1, 1, 1),
+    (5000, 4096, 64),
+    (70000, 256, 16),
 ]
 
 
