@@ -50,6 +50,10 @@
  *    padded with zeros, which does not change the product.
  *  - Results are deterministic: the schedule and every summation order are
  *    fixed, so the same inputs give the same bits on every run.
+ *  - Calls may be captured into a HIP graph: every entry point enqueues
+ *    kernels on `stream` only and no memset (zero fills are kernels).  The
+ *    workspace must then stay allocated for as long as the graph is
+ *    replayed.  The hs_profile_* timing calls are not for use under capture.
  */
 #ifndef HS_H
 #define HS_H
