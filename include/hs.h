@@ -167,7 +167,7 @@ hs_status hs_gemm(int64_t m, int64_t n, int64_t k, hs_dtype dtype, hs_schedule s
                   void *C, int64_t ldc, void *ws, size_t ws_bytes, void *stream);
 
 /* C[m, n] = A^T . B with A stored k x m (lda >= m), B k x n (ldb >= n).
- * The transposed product the paper says runs "on the same footing" (Abstract,
+ * The transposed product, which the paper says runs as efficiently (Abstract,
  * Sec. 8): the same schedule, with A's tiles read along its columns.
  * All dtypes; for the complex ones C = A^T B (transposed, not conjugated),
  * sizes and ld* in complex elements, pointers 8-byte aligned, and the
