@@ -1,33 +1,51 @@
-"""Literal simulator of the systolic and hyper-systolic matrix products, and
-of the two-array hyper-systolic recipe (Sec. 4.1).
+"""Ring simulator of the systolic and hyper-systolic matrix products, and of
+the two-array hyper-systolic recipe (Sec. 4.1).
 
 TEST INFRASTRUCTURE ONLY (never imported by the product path).
 
-A ring of p cells, each cell i holding column i of three skew-ordered p x p
-arrays a, b, c (Sec. 3.3.1).  The two data movements are exactly the paper's:
+The machine: a ring of p cells; cell i holds column i of three skew-ordered
+p x p arrays a, b, c (Sec. 3.3.1), i.e. storage row r of cell i holds the
+element ((i + r) mod p, i) (0-based).  It has one communication primitive,
+the circular shift of Sec. 5.1, Eq. CSHIFT1: after a shift by s, cell i holds
+what cell i + s held.  Reading a neighbouring storage row of the own column
+(cshift-col) is a local address offset, not communication.
 
-* ``cshift_row(x, k)`` -- Sec. 5.1, Eq. CSHIFT1: cell i receives the column of
-  cell i+k (1-based: a_{j,(i+k-1+n) mod n + 1}); interprocessor communication.
-* ``cshift_col(x, k)`` -- Sec. 5.1: inside every cell, storage row j reads
-  storage row j+k (a_{(j+k-1+n) mod n + 1, i}); a local address offset only.
+The product is driven by the three bases of Sec. 5.2.1 alone (0-based
+indices, K * K~ = p):
 
-``systolic`` runs Algorithm SYSTOLIC and ``hyper_systolic`` Algorithm
-HYPER-SYSTOLIC (Sec. 5.2.2) step by step in the paper's order and notation
-(1-based loop variables).  Elements may be numbers, numpy blocks (block
-mapping, Sec. 6.1: a p x p system of sub-matrices used like scalars) or the
-symbolic terms below, which record which products were formed.
+* base B = (0, -1, .., -1), K entries: storage rows of b fall into K classes
+  q mod K; class t is moved once, before any product, to the position
+  P_B(t) = b_0 + .. + b_t = -t of the base (a right shift by t);
+* base A = (0, K, .., K), K~ entries: a is moved by a_j before step j, so
+  during step j it sits at P_A(j) = j K;
+* base C = (0, 1, .., 1), K entries: the K auxiliary arrays c^0 .. c^{K-1}
+  (Sec. 5.2.2) are combined by a collector that starts as c^{K-1}, is moved
+  by c_t and then absorbs c^{t-1}, for t = K-1 .. 1.
+
+During step j, class t of b contributes storage row q = P_A(j) - P_B(t)
+(= j K + t), and each cell multiplies it with the a element whose storage
+row lies P_A(j) - P_B(t) rows above the c^t row it updates.  Derivation:
+after the moves, cell i holds a column (i + jK) of A and b column (i - t) of
+B, and both share the contraction index (i + jK) mod p; the product belongs
+to C column i - t, which the collector brings to cell i - t after t moves
+by +1, at the storage row that the skew order gives it.
+
+Elements may be numbers, numpy blocks (block mapping, Sec. 6.1: a p x p
+system of sub-matrices used like scalars) or the symbolic terms below,
+which record which products were formed.
 
 Readings of points the text leaves open (each pinned by brute force in the
 tests):
-* skew order: storage row r of cell i holds element ((i + r) mod p, i),
-  0-based, for all of a, b and c (Figs. TEMPLATE/TEMPLATE2 are missing);
-* pre-shift stride ``[(1-j) mod K]`` uses the remainder with the sign of the
-  dividend (Fortran MOD / C %), i.e. row j moves by -((j-1) mod K);
-* A moves by K (not K~) between the K~ groups, as in the algorithm listing.
+* skew order: the same for a, b and c (Figs. TEMPLATE/TEMPLATE2 are missing);
+* the pre-shift stride of storage row q is -(q mod K): the remainder taken
+  with the sign of the dividend (``preshift_stride``);
+* a moves by K (not K~) between steps, as base A states.
 """
 from collections import Counter
 
 import numpy as np
+
+from . import bases as _bases
 
 
 # ----------------------------------------------------------------------------
@@ -53,118 +71,130 @@ def from_skew(s):
 
 
 # ----------------------------------------------------------------------------
-# the two shift primitives (Sec. 5.1)
+# communication (Sec. 5.1, Eq. CSHIFT1)
 # ----------------------------------------------------------------------------
 class ShiftCounter:
-    """Counts interprocessor communication events (cshift-row calls)."""
+    """Counts interprocessor communication events (whole-array shifts)."""
 
     def __init__(self):
         self.events = 0
 
 
-def _fmod(a, b):
-    """Remainder with the sign of the dividend (Fortran MOD, C %)."""
-    r = abs(a) % abs(b)
-    return -r if a < 0 else r
-
-
 def cshift_row(x, k, counter=None):
-    """Eq. CSHIFT1 on the whole array: new[:, i] = old[:, (i + k) mod n]."""
-    n = x.shape[1]
-    out = np.empty_like(x)
-    for i1 in range(1, n + 1):                      # 1-based cell index
-        src = (i1 + k - 1 + n) % n + 1
-        out[:, i1 - 1] = x[:, src - 1]
+    """Shift a whole skew-ordered array along the ring: cell i receives the
+    column of cell i + k (Eq. CSHIFT1)."""
+    p = x.shape[1]
+    src = [(i + k) % p for i in range(p)]
+    out = x[:, src]
     if counter is not None:
         counter.events += 1
     return out
 
 
-def cshift_row_1(col_values, k, i1, n):
-    """Value arriving at cell i1 (1-based) when one storage row moves by k."""
-    return col_values[(i1 + k - 1 + n) % n]
+def preshift_stride(q, K):
+    """Stride by which storage row q of b is moved before the first product:
+    -(q mod K), the position P_B(q mod K) of base B = (0, -1, .., -1).  The
+    printed stride [(1 - j) mod K] (1-based row j = q + 1) gives the same
+    value when the remainder keeps the sign of the dividend."""
+    return -(q % K)
 
 
-def cshift_col(x, k, j1, i1):
-    """Element (j1, i1) (1-based) of cshift-col^k(x): x_{(j+k-1+n) mod n + 1, i}."""
-    n = x.shape[0]
-    return x[(j1 + k - 1 + n) % n, i1 - 1]
+def _zeros(p, zero):
+    c = np.empty((p, p), dtype=object)
+    for r in range(p):
+        for i in range(p):
+            c[r, i] = zero
+    return c
 
 
 # ----------------------------------------------------------------------------
-# Algorithm SYSTOLIC (Sec. 5.1)
+# the systolic product (Sec. 5.1): base A = (0, 1, .., 1), one array c
 # ----------------------------------------------------------------------------
 def systolic(A, B, zero, trace=None):
-    """C = A B on a ring of p cells, p steps, A travels by one each step."""
+    """C = A B on a ring of p cells in p steps: step j multiplies storage row
+    j of b with a, read j rows up, and a then moves by one cell.  The last
+    move only returns a to where it started.  Returns (C, shift_count)."""
     p = A.shape[0]
     a, b = to_skew(A), to_skew(B)
-    c = np.empty((p, p), dtype=object)
-    c[:, :] = [[zero for _ in range(p)] for _ in range(p)]
+    c = _zeros(p, zero)
     cnt = ShiftCounter()
-    for j in range(1, p + 1):
-        for i in range(1, p + 1):                   # foreach processor (SIMD)
-            for l in range(1, p + 1):
-                ae = cshift_col(a, 1 - j, l, i)
-                be = b[j - 1, i - 1]
-                c[l - 1, i - 1] = c[l - 1, i - 1] + ae * be
+    for j in range(p):
+        for i in range(p):
+            for n in range(p):
+                ae = a[(n - j) % p, i]
+                be = b[j, i]
+                c[n, i] = c[n, i] + ae * be
                 if trace is not None:
-                    trace.append((i, j, l, ae, be))
+                    trace.append((i, j, 0, n, ae, be))
         a = cshift_row(a, 1, cnt)
     return from_skew(c), cnt.events
 
 
 # ----------------------------------------------------------------------------
-# Algorithm HYPER-SYSTOLIC (Sec. 5.2.2)
+# the hyper-systolic product (Sec. 5.2.2) driven by the bases of Sec. 5.2.1
 # ----------------------------------------------------------------------------
+def _positions(base):
+    """Prefix sums of a base: where an array stands after each stride."""
+    return _bases.prefix_sums(base)
+
+
 def hyper_systolic(A, B, K, zero, trace=None):
     """C = A B with the regular bases A=(0,K,..,K), B=(0,-1,..,-1), C=(0,1,..,1).
 
     Returns (C, shift_count).  ``trace`` (a list) receives one record
-    (i, j, l, n, a_elem, b_elem) per block product formed, with 1-based cell
-    i, step j, auxiliary array l and storage row n.
+    (i, j, t, n, a_elem, b_elem) per product formed: 0-based cell i, step j,
+    auxiliary array t and storage row n of c^t.
     """
     p = A.shape[0]
     assert p % K == 0
-    Kt = p // K
+    base_a, base_b, base_c = _bases.matrix_product_bases(p, K)
+    pos_a = _positions(base_a)
+    pos_b = _positions(base_b)                      # 0, -1, .., -(K-1)
     a, b = to_skew(A), to_skew(B)
     cnt = ShiftCounter()
 
-    # pre-shift of B: storage row j moves by [(1-j) mod K]; all rows move at
-    # once, which the complexity count treats as one communication event.
-    nb = np.empty_like(b)
-    for j in range(1, p + 1):
-        stride = _fmod(1 - j, K)
-        for i in range(1, p + 1):
-            nb[j - 1, i - 1] = cshift_row_1(b[j - 1, :], stride, i, p)
-    b = nb
+    # base B: every storage row of b moves to its class position at once (the
+    # printed stride, read by preshift_stride); the complexity count
+    # (Thm. GAIN3) takes this as one event
+    moved = np.empty_like(b)
+    for q in range(p):
+        s = preshift_stride(q, K)
+        for i in range(p):
+            moved[q, i] = b[q, (i + s) % p]
+    b = moved
     cnt.events += 1
 
-    # K auxiliary result arrays C^1..C^K
-    c = {}
-    for l in range(1, K + 1):
-        c[l] = np.empty((p, p), dtype=object)
-        c[l][:, :] = [[zero for _ in range(p)] for _ in range(p)]
-
-    def multiply(j):
-        for i in range(1, p + 1):
-            for l in range(1, K + 1):
-                for n in range(1, p + 1):
-                    ae = cshift_col(a, 1 - (j - 1) * K - l, n, i)
-                    be = b[(j - 1) * K + l - 1, i - 1]
-                    c[l][n - 1, i - 1] = c[l][n - 1, i - 1] + ae * be
+    c = [_zeros(p, zero) for _ in range(K)]
+    for j, stride in enumerate(base_a):
+        if j > 0:                                   # base A: a moves by a_j
+            a = cshift_row(a, stride, cnt)
+        for t in range(K):
+            off = pos_a[j] - pos_b[t]               # = j K + t
+            q = off % p                             # the storage row of b in use
+            for i in range(p):
+                be = b[q, i]
+                for n in range(p):
+                    ae = a[(n - off) % p, i]
+                    c[t][n, i] = c[t][n, i] + ae * be
                     if trace is not None:
-                        trace.append((i, j, l, n, ae, be))
+                        trace.append((i, j, t, n, ae, be))
 
-    for j in range(1, Kt):                          # multiplication and shift of A
-        multiply(j)
-        a = cshift_row(a, K, cnt)
-    multiply(Kt)
+    # base C: the collector picks up c^{K-1}, .., c^0, moving by c_t before
+    # each pick-up
+    coll = c[K - 1]
+    for t in range(K - 1, 0, -1):
+        coll = cshift_row(coll, base_c[t], cnt)
+        coll = _add(c[t - 1], coll)
+    return from_skew(coll), cnt.events
 
-    for j in range(1, K):                           # back shift and accumulation
-        shifted = cshift_row(c[K - j + 1], 1, cnt)
-        c[K - j] = c[K - j] + shifted
 
-    return from_skew(c[1]), cnt.events
+def _add(x, y):
+    """Element-wise x + y of two object arrays (x's element first)."""
+    out = np.empty_like(x)
+    for r in range(x.shape[0]):
+        for i in range(x.shape[1]):
+            out[r, i] = x[r, i] + y[r, i]
+    return out
 
 
 # ----------------------------------------------------------------------------

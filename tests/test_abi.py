@@ -1,8 +1,8 @@
 """Host-side tests of the C ABI (CPU only: no kernel is launched).
 
 * the library loads and exports every function include/hs.h declares;
-* the schedule (index map) equals the event trace of the literal
-  Algorithm HYPER-SYSTOLIC simulator applied to C^T = B^T A^T;
+* the schedule (index map) equals the event trace of the ring simulator of
+  Algorithm HYPER-SYSTOLIC applied to C^T = B^T A^T;
 * every invalid argument is rejected with its status code before any launch.
 """
 import ctypes
@@ -65,7 +65,7 @@ def test_invalid_schedules(p, K):
 
 
 def _sim_table(p, K):
-    """(output stripe, contraction block) per (v, j, l) from the literal simulator.
+    """(output stripe, contraction block) per (v, j, l) from the ring simulator.
 
     The paper's algorithm keeps columns and moves A; the library keeps rows
     and moves B, i.e. it runs the algorithm on C^T = B^T A^T.  Paper element
@@ -76,7 +76,7 @@ def _sim_table(p, K):
     ev = {}
     for (i, j, l, n, ae, be) in trace:
         assert ae.c == be.r                     # contraction blocks agree
-        ev.setdefault((i - 1, j - 1, l - 1), set()).add((be.c, ae.c))
+        ev.setdefault((i, j, l), set()).add((be.c, ae.c))
     rows = []
     for v in range(p):
         for j in range(p // K):
@@ -88,7 +88,7 @@ def _sim_table(p, K):
 
 
 @pytest.mark.parametrize("p", [1, 2, 3, 4, 6, 8, 9, 12, 16])
-def test_schedule_table_equals_literal_algorithm(p):
+def test_schedule_table_equals_ring_simulation(p):
     for K in [d for d in range(1, p + 1) if p % d == 0]:
         assert np.array_equal(B.hs_schedule_table(p, K), _sim_table(p, K)), (p, K)
 

@@ -1,7 +1,8 @@
-"""Pins for the literal ring simulator and the hyper-systolic bases (CPU only).
+"""Pins for the ring simulator and the hyper-systolic bases (CPU only).
 
-The simulator executes Algorithms SYSTOLIC and HYPER-SYSTOLIC (Sec. 5) step by
-step with the cshift semantics of Eq. CSHIFT1.  These tests check it against
+The simulator runs the systolic and hyper-systolic products (Sec. 5) on a
+ring of cells with the shift of Eq. CSHIFT1, driven by the bases of
+Sec. 5.2.1.  These tests check it against
 the definition of the product (exactly, on small integers and symbolically),
 against the counting theorems, and against the facts the text states for the
 p = 4, K = 2 worked example (Sec. 3.2.3 and 3.3.3; the figures are missing).
@@ -90,8 +91,8 @@ def test_worked_example_p4_k2():
     """Facts stated in the text for p = 4, K = 2 (golden fixture, cited there)."""
     g = json.load(open(os.path.join(GOLDEN, "worked_example_p4_k2.json")))
     p, K = g["p"], g["K"]
-    # pre-shift strides [(1-j) mod K] for storage rows j = 1..p
-    strides = [ring._fmod(1 - j, K) for j in range(1, p + 1)]
+    # pre-shift strides of storage rows j = 1..p (0-based q = j - 1)
+    strides = [ring.preshift_stride(j - 1, K) for j in range(1, p + 1)]
     moved = [j for j, s in zip(range(1, p + 1), strides) if abs(s) == 1]
     still = [j for j, s in zip(range(1, p + 1), strides) if s == 0]
     assert moved == g["preshift_rows_moved_by_one_1based"]
@@ -123,8 +124,8 @@ def test_worked_example_p4_k2():
 
 def test_floored_mod_reading_fails():
     """Reading the pre-shift with a floored mod breaks the product for 1 < K < p."""
-    orig = ring._fmod
-    ring._fmod = lambda a, b: a % b
+    orig = ring.preshift_stride
+    ring.preshift_stride = lambda q, K: (-q) % K      # [(1 - j) mod K], floored
     try:
         failures = 0
         for p in (4, 6, 8, 9):
@@ -135,7 +136,7 @@ def test_floored_mod_reading_fails():
                     failures += int(not (C == A.dot(B)).all())
         assert failures == sum(1 for p in (4, 6, 8, 9) for K in _divisors(p) if 1 < K < p)
     finally:
-        ring._fmod = orig
+        ring.preshift_stride = orig
 
 
 def test_stride_Ktilde_reading_fails_when_K_differs():
