@@ -9,6 +9,8 @@ G ~ N(0, 1), seeded, resident in HBM before the timed region.
 Prints ONE JSON line.  ``value`` is the useful TFLOP/s of the split-BF16
 form (3 * 2 n^3 flops per step over the timed wall clock); the plain FP32
 form of the same step is measured beside it under ``comparison``.
+``accuracy`` holds, for both forms, the errors of the last timed step's C,
+dA and dB against the FP64 oracle rows that the CPU baseline computes.
 """
 import argparse
 import json
@@ -78,6 +80,8 @@ STORAGE = {"bf16": "bfloat16", "f16": "float16", "f64": "float64"}
 
 
 def run_form(hs, torch, A, B, G, form, p, K, steps, warmup):
+    """Times ``steps`` steps; returns (wall s, summed main-kernel ms,
+    main-kernel launches, (C, dA, dB) of the last timed step)."""
     if form in STORAGE:   # the 16-bit and FP64 forms take inputs of their own type
         dt = getattr(torch, STORAGE[form])
         A, B, G = A.to(dt), B.to(dt), G.to(dt)
@@ -88,15 +92,41 @@ def run_form(hs, torch, A, B, G, form, p, K, steps, warmup):
     hs.hs_profile_begin()
     t0 = time.perf_counter()
     for _ in range(steps):
-        step(hs, A, B, G, form, p, K)
+        outs = step(hs, A, B, G, form, p, K)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     kern_ms, launches = hs.hs_profile_end()
-    return wall, kern_ms, launches
+    return wall, kern_ms, launches, outs
+
+
+def accuracy(outs, ref, n_elem=64):
+    """err_row and err_peak of the timed step's C, dA and dB on the rows the
+    CPU baseline sampled, and err_elem (|dC| over the sum of absolute
+    products) on the first ``n_elem`` of them."""
+    import numpy as np
+    import torch
+    import oracle
+    from oracle.metrics import err_elem, err_peak, err_row
+    rows_m, rows_k = ref["rows_m"], ref["rows_k"]
+    A64, B64, G64 = ref["A"], ref["B"], ref["G"]
+    aA, aB, aG = np.abs(A64), np.abs(B64), np.abs(G64)
+    e = rows_m[:n_elem], rows_k[:n_elem]
+    absp = {"C": lambda: oracle.gemm_rows(aA, aB, e[0]),
+            "dA": lambda: oracle.grad_a_rows(aG, aB, e[0]),
+            "dB": lambda: oracle.grad_b_rows(aA, aG, e[1])}
+    res = {}
+    for name, out, rows in zip(("C", "dA", "dB"), outs, (rows_m, rows_m, rows_k)):
+        got = out.index_select(0, torch.as_tensor(rows, device=out.device)).double().cpu().numpy()
+        r = ref[name]
+        res[name] = {"err_row": err_row(got, r), "err_peak": err_peak(got, r),
+                     "err_elem": err_elem(got[:n_elem], r[:n_elem], absp[name]())}
+    res["rows"] = "%d sampled rows of each output (err_elem on %d of them)" % (len(rows_m), min(n_elem, len(rows_m)))
+    return res
 
 
 def cpu_baseline(A64, B64, G64, target_s):
-    """The FP64 oracle on sampled rows of C, dA and dB (bounded sample)."""
+    """The FP64 oracle on sampled rows of C, dA and dB (bounded sample).
+    Returns (the baseline record, the oracle rows for the accuracy check)."""
     import oracle
     from paper_cs_9809105_amd import inputs
     m, k = A64.shape
@@ -118,9 +148,9 @@ def cpu_baseline(A64, B64, G64, target_s):
     rows_m = inputs.sample_rows(m, nrows, seed=8)
     rows_k = inputs.sample_rows(k, nrows, seed=8)
     t0 = time.perf_counter()
-    oracle.gemm_rows(A64, B64, rows_m)
-    oracle.grad_a_rows(G64, B64, rows_m)
-    oracle.grad_b_rows(A64, G64, rows_k)
+    refC = oracle.gemm_rows(A64, B64, rows_m)
+    refdA = oracle.grad_a_rows(G64, B64, rows_m)
+    refdB = oracle.grad_b_rows(A64, G64, rows_k)
     dt = time.perf_counter() - t0
     flops = 2.0 * nrows * (n * k + n * k + m * n)
     # the same oracle on one thread, over a smaller sample (one row per core)
@@ -134,10 +164,13 @@ def cpu_baseline(A64, B64, G64, target_s):
     finally:
         oracle.set_threads(cores)
     flops1 = 2.0 * cal * (n * k + n * k + m * n)
-    return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
-            "value_1thread": flops1 / dt1 / 1e12,
-            "sample": "%d sampled rows of each of C, dA, dB (M=%d Kd=%d N=%d, FP64 triple loop, %.1f s); "
-                      "1-thread figure on %d rows (%.1f s)" % (nrows, m, k, n, dt, cal, dt1)}
+    rec = {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
+           "value_1thread": flops1 / dt1 / 1e12,
+           "sample": "%d sampled rows of each of C, dA, dB (M=%d Kd=%d N=%d, FP64 triple loop, %.1f s); "
+                     "1-thread figure on %d rows (%.1f s)" % (nrows, m, k, n, dt, cal, dt1)}
+    ref = {"rows_m": rows_m, "rows_k": rows_k, "C": refC, "dA": refdA, "dB": refdB,
+           "A": A64, "B": B64, "G": G64}
+    return rec, ref
 
 
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "mm_kernel_split3_f32_n8192_traffic.json")
@@ -206,12 +239,19 @@ def gemv_main(args):
         reps, t_cpu = 0, 0.0
         t0 = time.perf_counter()
         while t_cpu < min(args.cpu_seconds, 5.0):
-            oracle.gemv(Ah, xh)
+            yref = oracle.gemv(Ah, xh)
             reps += 1
             t_cpu = time.perf_counter() - t0
         cpu = {"value": nbytes * reps / t_cpu / 1e9, "unit": "GB/s", "kind": "oracle",
                "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)),
                "sample": "%d full %dx%d FP64 matrix-vector products (%.1f s)" % (reps, n, n, t_cpu)}
+        from oracle.metrics import err_elem, err_peak, err_row
+        yg = y.double().cpu().numpy()[None, :]
+        acc = {"f32": {"y": {"err_row": err_row(yg, yref[None, :]), "err_peak": err_peak(yg, yref[None, :]),
+                             "err_elem": err_elem(yg, yref[None, :], oracle.gemv(abs(Ah), abs(xh))[None, :])},
+                       "rows": "all %d elements of the last timed y" % n}}
+    else:
+        acc = None
     print(json.dumps({
         "metric": "GB/s of y = A.x (A %dx%d FP32, read once)" % (n, n),
         "value": nbytes * args.steps / wall / 1e9, "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
@@ -222,6 +262,7 @@ def gemv_main(args):
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK["hbm_gbs"], "unit": "GB/s",
                      "frac": achieved / PEAK["hbm_gbs"], "traffic": None, "kernel": "gemv_kernel",
                      "avg_kernel_ms": avg, "launches": launches},
+        "accuracy": acc,
         "cpu_baseline": cpu}))
 
 
@@ -265,13 +306,21 @@ def nbody_main(args):
         rows = max(1, min(n, int(rows * args.cpu_seconds / max(t_cal, 1e-4))))
         idx = inputs.sample_rows(n, rows, seed=9)
         t1 = time.perf_counter()
-        oracle.nbody_rows(Xh, e2, idx)
+        ref, scale = oracle.nbody_rows(Xh, e2, idx)
         t_cpu = time.perf_counter() - t1
         cpu = {"value": rows * (n - 1) / t_cpu / 1e9, "unit": "Ginteractions/s", "kind": "oracle",
                "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)),
                "value_tflops": NBODY_FLOPS * rows * (n - 1) / t_cpu / 1e12,
                "sample": "%d sampled bodies, each against all %d others (FP64 direct sum, %.1f s)"
                          % (rows, n - 1, t_cpu)}
+        got = out.double().cpu().numpy()[idx]
+        # acceleration error over the sum of the terms' lengths, potential
+        # error relative to the potential (its terms have one sign)
+        acc = {"f32": {"err_accel": float((np.abs(got[:, :3] - ref[:, :3]).max(axis=1) / scale).max()),
+                       "err_phi": float((np.abs(got[:, 3] - ref[:, 3]) / np.abs(ref[:, 3])).max()),
+                       "rows": "the %d sampled bodies of the last timed call" % rows}}
+    else:
+        acc = None
     print(json.dumps({
         "metric": "body-body interactions per second, all-pairs gravity of n=%d bodies (FP32)" % n,
         "value": pairs * args.steps / wall / 1e9, "unit": "Ginteractions/s", "n_gpus": 1,
@@ -284,6 +333,7 @@ def nbody_main(args):
         "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_F32_PEAK, "unit": "TFLOP/s",
                      "frac": achieved / VALU_F32_PEAK, "traffic": None, "kernel": "nbody_kernel",
                      "flops_per_interaction": NBODY_FLOPS, "avg_kernel_ms": avg, "launches": launches},
+        "accuracy": acc,
         "cpu_baseline": cpu}))
 
 
@@ -312,20 +362,20 @@ def complex_main(args):
         hs.hs_profile_begin()
         t0 = time.perf_counter()
         for _ in range(steps):
-            step(hs, A, B, G, fm, p, K)
+            outs = step(hs, A, B, G, fm, p, K)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         ms, launches = hs.hs_profile_end()
-        return wall, ms / max(launches, 1), launches
+        return wall, ms / max(launches, 1), launches, outs[0]
 
     useful = 3 * 8.0 * n ** 3                      # per step
-    wall, avg, launches_c = timed(form, args.steps, args.warmup)
+    wall, avg, launches_c, C_last = timed(form, args.steps, args.warmup)
     mfma = (6 if form == "c32_split3_bf16" else 1) * 8.0 * n ** 3 * 3 * args.steps   # all timed launches
     peak = PEAK["bf16" if form == "c32_split3_bf16" else "f32"]
     achieved = mfma / (avg * launches_c * 1e-3) / 1e12
     comparison = None
     if args.compare and form != "c32":
-        w2, a2, _ = timed("c32", max(2, args.steps // 2), 1)
+        w2, a2, _, _ = timed("c32", max(2, args.steps // 2), 1)
         comparison = {"c32": {"value": useful * max(2, args.steps // 2) / w2 / 1e12, "avg_main_kernel_ms": a2}}
     cpu = None
     if args.cpu_seconds > 0:
@@ -337,16 +387,25 @@ def complex_main(args):
         oracle.complex_gemm_rows(Ah, Bh, inputs.sample_rows(n, cores, seed=7))
         t_cal = time.perf_counter() - t0
         nrows = max(cores, min(n, int(cores * args.cpu_seconds / max(t_cal, 1e-6)) // cores * cores))
+        rows = inputs.sample_rows(n, nrows, seed=8)
         t0 = time.perf_counter()
-        oracle.complex_gemm_rows(Ah, Bh, inputs.sample_rows(n, nrows, seed=8))
+        ref = oracle.complex_gemm_rows(Ah, Bh, rows)
         dt = time.perf_counter() - t0
         cpu = {"value": 8.0 * nrows * n * n / dt / 1e12, "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
                "sample": "%d sampled rows of C (n=%d complex, FP64 parts, %.1f s)" % (nrows, n, dt)}
+        from oracle.metrics import err_elem, err_peak, err_row
+        got = C_last.index_select(0, torch.as_tensor(rows, device=C_last.device)).cpu().numpy().astype(np.complex128)
+        ne = min(16, nrows)
+        acc = {form: {"C": {"err_row": err_row(got, ref), "err_peak": err_peak(got, ref),
+                            "err_elem": err_elem(got[:ne], ref[:ne], oracle.complex_absprod_rows(Ah, Bh, rows[:ne]))},
+                      "rows": "%d sampled rows of the last timed C (err_elem on %d)" % (nrows, ne)}}
+    else:
+        acc = None
     print(json.dumps({
         "metric": "TFLOP/s at n=%d complex64, fwd+bwd: %s" % (n, form),
         "value": useful * args.steps / wall / 1e12, "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": wall * 1e3 / args.steps, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "bf16x3" if form == "c32_split3_bf16" else "f32",
+        "scaling": "weak", "vs_baseline": None, "dtype": form,
         "data": "synthetic",
         "config": {"workload": "hyper-systolic complex C=A.B + dA=G.B^H + dB=A^H.G, square n=%d, "
                                "N(0,1) real and imaginary parts" % n,
@@ -354,7 +413,7 @@ def complex_main(args):
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": None, "kernel": "mm_kernel (main MFMA loop)",
                      "avg_kernel_ms": avg, "launches": launches_c},
-        "comparison": comparison, "cpu_baseline": cpu}))
+        "comparison": comparison, "accuracy": acc, "cpu_baseline": cpu}))
 
 
 def main():
@@ -399,7 +458,7 @@ def main():
         del src, dst
 
     useful = 3 * 2.0 * m * kd * n
-    wall, kern_ms, launches = run_form(hs, torch, A, B, G, args.form, p, K, args.steps, args.warmup)
+    wall, kern_ms, launches, outs = run_form(hs, torch, A, B, G, args.form, p, K, args.steps, args.warmup)
     ms_step = wall * 1e3 / args.steps
     value = useful * args.steps / wall / 1e12
     avg_kernel_ms = kern_ms / max(launches, 1)
@@ -409,16 +468,22 @@ def main():
     achieved = mfma_flops / (kern_ms * 1e-3) / 1e12
     peak = PEAK[MFMA_PEAK_KEY[args.form]]
 
+    # the timed step's outputs, kept on the GPU for the accuracy check
+    outs_cmp = None
     comparison = None
     if args.compare:
-        w2, k2, l2 = run_form(hs, torch, A, B, G, args.compare, p, K, max(2, args.steps // 2), 1)
         s2 = max(2, args.steps // 2)
+        w2, k2, l2, outs_cmp = run_form(hs, torch, A, B, G, args.compare, p, K, s2, 1)
         comparison = {args.compare: {"value": useful * s2 / w2 / 1e12, "ms_per_step": w2 * 1e3 / s2,
                                      "avg_main_kernel_ms": k2 / max(l2, 1)}}
 
     cpu = None
+    acc = None
     if args.cpu_seconds > 0:
-        cpu = cpu_baseline(A64, B64, G64, args.cpu_seconds)
+        cpu, ref = cpu_baseline(A64, B64, G64, args.cpu_seconds)
+        acc = {args.form: accuracy(outs, ref)}
+        if outs_cmp is not None:
+            acc[args.compare] = accuracy(outs_cmp, ref)
 
     square = m == kd == n
     shape_txt = "square n=%d" % n if square else "A %dx%d, B %dx%d" % (m, kd, kd, n)
@@ -427,7 +492,7 @@ def main():
         "metric": "TFLOP/s at n=8192: split-BF16 (FP32-accurate) vs plain FP32 GEMM; fwd+bwd",
         "value": value, "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "bf16x3" if args.form == "split3_bf16" else args.form, "data": "synthetic",
+        "dtype": args.form, "data": "synthetic",
         "config": {"workload": "hyper-systolic C=A.B + dA=G.B^T + dB=A^T.G, %s, %s, N(0,1) G"
                                % (shape_txt, in_txt),
                    "M": m, "Kd": kd, "N": n, "p": p, "K": K, "form": args.form},
@@ -436,6 +501,7 @@ def main():
                      "kernel": "mm_kernel (main MFMA loop)", "avg_kernel_ms": avg_kernel_ms,
                      "launches": launches},
         "comparison": comparison,
+        "accuracy": acc,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

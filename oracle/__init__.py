@@ -218,3 +218,38 @@ def nbody_rows(bodies, eps2, rows):
     sc = np.empty(len(r), np.float64)
     _load().hs_oracle_nbody_rows(n, _p(X), float(eps2), rp, len(r), _p(out), _p(sc))
     return out, sc
+
+
+# ---------------------------------------------------------------------------
+# sums of absolute products: the scale of the element-wise error bounds
+# (every rounding-error bound of a dot product is a multiple of
+# sum_k |a_ik| |b_kj|)
+# ---------------------------------------------------------------------------
+def absprod(A, B):
+    """(|A| |B|)_ij = sum_k |a_ik| |b_kj| (A m x k, B k x n)."""
+    return gemm(np.abs(_d(A)), np.abs(_d(B)))
+
+
+def absprod_rows(A, B, rows):
+    """Rows ``rows`` of |A| |B|."""
+    return gemm_rows(np.abs(_d(A)), np.abs(_d(B)), rows)
+
+
+def complex_absprod(A, B):
+    """Sums of absolute real products of the complex product A . B, as
+    re + 1j im: the real part of c_ij is sum_k (re a re b - im a im b), so
+    its scale is sum_k (|re a||re b| + |im a||im b|); the imaginary part's
+    is sum_k (|re a||im b| + |im a||re b|)."""
+    A = np.asarray(A, np.complex128)
+    B = np.asarray(B, np.complex128)
+    Ar, Ai, Br, Bi = np.abs(A.real), np.abs(A.imag), np.abs(B.real), np.abs(B.imag)
+    return (gemm(Ar, Br) + gemm(Ai, Bi)) + 1j * (gemm(Ar, Bi) + gemm(Ai, Br))
+
+
+def complex_absprod_rows(A, B, rows):
+    """Rows ``rows`` of complex_absprod(A, B)."""
+    A = np.asarray(A, np.complex128)
+    B = np.asarray(B, np.complex128)
+    Ar, Ai, Br, Bi = np.abs(A.real), np.abs(A.imag), np.abs(B.real), np.abs(B.imag)
+    return ((gemm_rows(Ar, Br, rows) + gemm_rows(Ai, Bi, rows))
+            + 1j * (gemm_rows(Ar, Bi, rows) + gemm_rows(Ai, Br, rows)))

@@ -2,9 +2,19 @@
 
 err_row  = max_r ||C_r - Chat_r||_2 / ||Chat_r||_2
            (relative error per output row; insensitive to per-row scales)
+err_peak = max_r max_j |C_rj - Chat_rj| / (||Chat_r||_2 / sqrt(n))
+           (the largest single-element error, relative to its row's rms
+           magnitude: a lone wrong element of an n-wide row moves err_row by
+           only 1/sqrt(n) of what it moves err_peak)
 err_elem = max_ij |C_ij - Chat_ij| / (|A| |B|)_ij
-           (error relative to the sum of absolute products, the natural
-           scale of a rounding error in a dot product)
+           (error relative to the sum of absolute products, the scale of
+           every rounding-error bound of a dot product; for complex results
+           the real and imaginary parts are taken separately, each against
+           its own sum of absolute products, given as absprod.real and
+           absprod.imag)
+
+A row whose reference is all zeros is measured in absolute terms (its
+denominator is taken as 1), and so is an element whose absprod is zero.
 """
 import numpy as np
 
@@ -16,17 +26,37 @@ def _promote(C, ref):
     return np.asarray(C, dt), np.asarray(ref, dt)
 
 
-def err_row(C, ref):
+def _rows(C, ref):
     C, ref = _promote(C, ref)
     if C.ndim == 1:
         C, ref = C[None, :], ref[None, :]
+    return C, ref
+
+
+def err_row(C, ref):
+    C, ref = _rows(C, ref)
     num = np.linalg.norm(C - ref, axis=1)
     den = np.linalg.norm(ref, axis=1)
     den = np.where(den == 0, 1.0, den)
     return float(np.max(num / den)) if C.size else 0.0
 
 
+def err_peak(C, ref):
+    C, ref = _rows(C, ref)
+    if not C.size:
+        return 0.0
+    rms = np.linalg.norm(ref, axis=1) / np.sqrt(C.shape[1])
+    rms = np.where(rms == 0, 1.0, rms)
+    return float(np.max(np.abs(C - ref).max(axis=1) / rms))
+
+
 def err_elem(C, ref, absprod):
     C, ref = _promote(C, ref)
-    den = np.where(absprod == 0, 1.0, absprod)
-    return float(np.max(np.abs(C - ref) / den)) if C.size else 0.0
+    if not C.size:
+        return 0.0
+    if np.iscomplexobj(C):
+        ap = np.asarray(absprod, np.complex128)
+        return max(err_elem(C.real, ref.real, ap.real), err_elem(C.imag, ref.imag, ap.imag))
+    ap = np.asarray(absprod, np.float64)
+    den = np.where(ap == 0, 1.0, ap)
+    return float(np.max(np.abs(C - ref) / den))

@@ -138,6 +138,23 @@ def _out_type(dt):
     return "float64" if dt == HS_F64 else "float32"
 
 
+def row_layout(shape, strides, name="tensor"):
+    """Leading dimension of a 2-D row-major view with this shape and these
+    strides (in elements), or ValueError if the C ABI cannot address it: the
+    elements of a row must be contiguous, and rows may not overlap (a view
+    whose row stride is below its row length, such as an expanded tensor
+    with stride 0, would make the library read past its storage)."""
+    rows, cols = shape
+    if rows == 0 or cols == 0:
+        return max(cols, 1)
+    if cols > 1 and strides[1] != 1:
+        raise ValueError("%s must have unit stride along rows" % name)
+    if rows > 1 and strides[0] < cols:
+        raise ValueError("%s has overlapping rows (row stride %d < row length %d); pass a "
+                         "contiguous copy" % (name, strides[0], cols))
+    return max(strides[0] if rows > 1 else cols, cols, 1)
+
+
 def _mat(t, name, dt):
     torch = _torch()
     if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
@@ -146,15 +163,23 @@ def _mat(t, name, dt):
         raise ValueError("%s must be 2-D" % name)
     if t.dtype != getattr(torch, IN_TYPES[dt]):
         raise TypeError("%s must be %s for this dtype, got %s" % (name, IN_TYPES[dt], t.dtype))
-    if t.numel() and t.stride(1) != 1:
-        raise ValueError("%s must have unit stride along rows" % name)
-    return t.data_ptr(), max(t.stride(0), t.shape[1], 1)
+    return t.data_ptr(), row_layout(tuple(t.shape), t.stride(), name)
 
 
 def _stream(stream):
     torch = _torch()
     s = torch.cuda.current_stream() if stream is None else stream
     return ctypes.c_void_p(s.cuda_stream)
+
+
+def _on(stream):
+    """Context under which the workspace, temporaries and outputs of a call
+    are allocated: the caller's stream, so that PyTorch's caching allocator
+    does not hand their memory to other work while the call's kernels, which
+    run on that stream, still use it."""
+    import contextlib
+    torch = _torch()
+    return torch.cuda.stream(stream) if stream is not None else contextlib.nullcontext()
 
 
 def _workspace(nbytes, device):
@@ -172,8 +197,7 @@ def _new_out(shape, dt, device, out, name):
         return torch.empty(shape, dtype=getattr(torch, _out_type(dt)), device=device)
     if tuple(out.shape) != tuple(shape) or out.dtype != getattr(torch, _out_type(dt)):
         raise ValueError("%s must be %s %s" % (name, shape, _out_type(dt)))
-    if out.numel() and out.stride(1) != 1:
-        raise ValueError("%s must have unit stride along rows" % name)
+    row_layout(tuple(out.shape), out.stride(), name)
     return out
 
 
@@ -186,11 +210,12 @@ def hs_gemm(A, B, dtype="f32", p=1, K=0, out=None, stream=None):
     k2, n = B.shape
     if k != k2:
         raise ValueError("inner dimensions differ: %d vs %d" % (k, k2))
-    C = _new_out((m, n), dt, A.device, out, "out")
-    ws, nb = _workspace(hs_workspace_size(HS_OP_GEMM, m, n, k, dt, p, K), A.device)
-    st = lib().hs_gemm(m, n, k, dt, hs_schedule(p, K), a, lda, b, ldb, C.data_ptr(),
-                       max(C.stride(0), n, 1), ws.data_ptr() if ws is not None else None, nb,
-                       _stream(stream))
+    with _on(stream):
+        C = _new_out((m, n), dt, A.device, out, "out")
+        ws, nb = _workspace(hs_workspace_size(HS_OP_GEMM, m, n, k, dt, p, K), A.device)
+        st = lib().hs_gemm(m, n, k, dt, hs_schedule(p, K), a, lda, b, ldb, C.data_ptr(),
+                           row_layout((m, n), C.stride()), ws.data_ptr() if ws is not None else None, nb,
+                           _stream(stream))
     _check(st, "hs_gemm")
     return C
 
@@ -204,11 +229,12 @@ def hs_gemm_tn(A, B, dtype="f32", p=1, K=0, out=None, stream=None):
     k2, n = B.shape
     if k != k2:
         raise ValueError("contraction dimensions differ: %d vs %d" % (k, k2))
-    C = _new_out((m, n), dt, A.device, out, "out")
-    ws, nb = _workspace(hs_workspace_size(HS_OP_GEMM_TN, m, n, k, dt, p, K), A.device)
-    st = lib().hs_gemm_tn(m, n, k, dt, hs_schedule(p, K), a, lda, b, ldb, C.data_ptr(),
-                          max(C.stride(0), n, 1), ws.data_ptr() if ws is not None else None, nb,
-                          _stream(stream))
+    with _on(stream):
+        C = _new_out((m, n), dt, A.device, out, "out")
+        ws, nb = _workspace(hs_workspace_size(HS_OP_GEMM_TN, m, n, k, dt, p, K), A.device)
+        st = lib().hs_gemm_tn(m, n, k, dt, hs_schedule(p, K), a, lda, b, ldb, C.data_ptr(),
+                              row_layout((m, n), C.stride()), ws.data_ptr() if ws is not None else None, nb,
+                              _stream(stream))
     _check(st, "hs_gemm_tn")
     return C
 
@@ -221,12 +247,13 @@ def hs_gemv(A, x, dtype="f32", p=1, K=0, out=None, stream=None):
     m, n = A.shape
     if x.dim() != 1 or x.shape[0] != n or x.dtype != A.dtype or x.device != A.device:
         raise ValueError("x must be a length-%d vector of A's dtype on A's device" % n)
-    x = x.contiguous()
-    y = torch.empty(m, dtype=A.dtype, device=A.device) if out is None else out
-    if y.shape != (m,) or y.dtype != A.dtype or (m and y.stride(0) != 1):
-        raise ValueError("out must be a contiguous length-%d vector" % m)
-    st = lib().hs_gemv(m, n, dt, hs_schedule(p, K), a, lda, x.data_ptr(), y.data_ptr(),
-                       None, 0, _stream(stream))
+    with _on(stream):
+        x = x.contiguous()
+        y = torch.empty(m, dtype=A.dtype, device=A.device) if out is None else out
+        if y.shape != (m,) or y.dtype != A.dtype or (m and y.stride(0) != 1):
+            raise ValueError("out must be a contiguous length-%d vector" % m)
+        st = lib().hs_gemv(m, n, dt, hs_schedule(p, K), a, lda, x.data_ptr(), y.data_ptr(),
+                           None, 0, _stream(stream))
     _check(st, "hs_gemv")
     return y
 
@@ -243,13 +270,14 @@ def hs_gemm_backward(A, B, G, dtype="f32", p=1, K=0, need_a=True, need_b=True, s
     if k != k2 or tuple(G.shape) != (m, n):
         raise ValueError("shape mismatch: A %s, B %s, G %s" % (tuple(A.shape), tuple(B.shape), tuple(G.shape)))
     ot = getattr(torch, _out_type(dt))
-    dA = torch.empty((m, k), dtype=ot, device=A.device) if need_a else None
-    dB = torch.empty((k, n), dtype=ot, device=A.device) if need_b else None
-    ws, nb = _workspace(hs_workspace_size(HS_OP_BACKWARD, m, n, k, dt, p, K), A.device)
-    st = lib().hs_gemm_backward(m, n, k, dt, hs_schedule(p, K), a, lda, b, ldb, g, ldg,
-                                dA.data_ptr() if dA is not None else None, max(k, 1),
-                                dB.data_ptr() if dB is not None else None, max(n, 1),
-                                ws.data_ptr() if ws is not None else None, nb, _stream(stream))
+    with _on(stream):
+        dA = torch.empty((m, k), dtype=ot, device=A.device) if need_a else None
+        dB = torch.empty((k, n), dtype=ot, device=A.device) if need_b else None
+        ws, nb = _workspace(hs_workspace_size(HS_OP_BACKWARD, m, n, k, dt, p, K), A.device)
+        st = lib().hs_gemm_backward(m, n, k, dt, hs_schedule(p, K), a, lda, b, ldb, g, ldg,
+                                    dA.data_ptr() if dA is not None else None, max(k, 1),
+                                    dB.data_ptr() if dB is not None else None, max(n, 1),
+                                    ws.data_ptr() if ws is not None else None, nb, _stream(stream))
     _check(st, "hs_gemm_backward")
     return dA, dB
 
@@ -270,13 +298,14 @@ def hs_nbody(bodies, eps2=0.0, dtype=None, p=1, K=0, out=None, stream=None):
     dt = _dt(dtype)
     if bodies.dtype != getattr(torch, IN_TYPES[dt]) or dt not in (HS_F32, HS_F64):
         raise TypeError("bodies must be float32 (f32) or float64 (f64)")
-    bodies = bodies.contiguous()
     n = bodies.shape[0]
-    o = torch.empty((n, 4), dtype=bodies.dtype, device=bodies.device) if out is None else out
-    if tuple(o.shape) != (n, 4) or o.dtype != bodies.dtype or (n and not o.is_contiguous()):
-        raise ValueError("out must be a contiguous n x 4 tensor of the bodies' dtype")
-    ws, nb = _workspace(hs_workspace_size(HS_OP_NBODY, n, 0, 0, dt, p, K), bodies.device)
-    st = lib().hs_nbody(n, dt, hs_schedule(p, K), bodies.data_ptr(), float(eps2), o.data_ptr(),
-                        ws.data_ptr() if ws is not None else None, nb, _stream(stream))
+    with _on(stream):
+        bodies = bodies.contiguous()
+        o = torch.empty((n, 4), dtype=bodies.dtype, device=bodies.device) if out is None else out
+        if tuple(o.shape) != (n, 4) or o.dtype != bodies.dtype or (n and not o.is_contiguous()):
+            raise ValueError("out must be a contiguous n x 4 tensor of the bodies' dtype")
+        ws, nb = _workspace(hs_workspace_size(HS_OP_NBODY, n, 0, 0, dt, p, K), bodies.device)
+        st = lib().hs_nbody(n, dt, hs_schedule(p, K), bodies.data_ptr(), float(eps2), o.data_ptr(),
+                            ws.data_ptr() if ws is not None else None, nb, _stream(stream))
     _check(st, "hs_nbody")
     return o

@@ -40,3 +40,60 @@ def host(t):
 def poisoned(shape, dtype, device="cuda"):
     """Output buffer pre-filled with NaN to expose elements never written."""
     return torch.full(shape, float("nan"), dtype=dtype, device=device)
+
+
+# ---------------------------------------------------------------------------
+# parity gates
+# ---------------------------------------------------------------------------
+# err_row (relative 2-norm per row): the stated tolerances of each form
+ROW_TOL = {"f64": 1e-12, "f32": 1e-5, "split3_bf16": 1e-5, "bf16": 1.5e-2, "f16": 3e-3,
+           "fp8_e4m3": 1e-1, "fp8_e4m3_r1": 1e-2, "c32": 1e-5, "c32_split3_bf16": 1e-5}
+# err_peak (largest element error over its row's rms) for the FP32-accurate
+# and FP64 forms: a lone wrong element of an n-wide row moves err_row by
+# only 1/sqrt(n) of this, so the row gate alone would let it pass
+PEAK_TOL = {"f64": 1e-12, "f32": 5e-5, "split3_bf16": 5e-5, "c32": 5e-5, "c32_split3_bf16": 5e-5}
+# Element-wise bound |dC_ij| <= c k u (|A||B|)_ij, u the unit roundoff of the
+# accumulator (FP32 2^-24, FP64 2^-53), k the contraction length:
+#   * every product a_ik b_kj of the stored inputs enters one accumulator
+#     chain; each addition errs by less than one unit in the last place of
+#     its result (< 2u relative, also where the MFMA truncates the aligned
+#     smaller addend), and every partial sum is at most sum |a||b|;
+#   * plain forms: at most k additions plus the final rounding:
+#     (2k + 1) u <= 3 k u;
+#   * split-BF16: 6 products per term, so at most 6k additions (12 k u), plus
+#     the dropped pieces a1 b2 + a2 b1 + a2 b2 and the residual of the
+#     3-piece split (each operand a = a0 + a1 + a2 + r, |r| <= u |a|):
+#     under 4.1 u per term, and the kept pieces' absolute sum exceeds
+#     |a||b| by at most 2^-6: (13 k + 5) u;
+#   * complex forms run as a real product of contraction 2k.
+ELEM_C = {"f64": (3, 0), "f32": (3, 0), "bf16": (3, 0), "f16": (3, 0), "split3_bf16": (13, 5)}
+UNIT = {"f64": 2.0 ** -53, "f32": 2.0 ** -24, "bf16": 2.0 ** -24, "f16": 2.0 ** -24, "split3_bf16": 2.0 ** -24}
+COMPLEX_BASE = {"c32": "f32", "c32_split3_bf16": "split3_bf16"}
+
+
+def elem_bound(dt, k):
+    """(c k + d) u of the element-wise gate for form ``dt`` and contraction ``k``."""
+    if dt in COMPLEX_BASE:
+        return elem_bound(COMPLEX_BASE[dt], 2 * k)
+    c, d = ELEM_C[dt]
+    return (c * max(int(k), 1) + d) * UNIT[dt]
+
+
+def check(got, ref, dt, k=None, absprod=None, what=""):
+    """Assert the parity gates of form ``dt``: err_row always, err_peak for
+    the FP32-accurate and FP64 forms, err_elem <= c k u when ``absprod`` (the
+    oracle's sum of absolute products of the same elements) is given.
+    Returns the measured (err_row, err_peak, err_elem)."""
+    from oracle.metrics import err_elem, err_peak, err_row
+    assert not np.isnan(np.asarray(got)).any(), (what, "NaN in the result")
+    er = err_row(got, ref)
+    ep = err_peak(got, ref)
+    ee = err_elem(got, ref, absprod) if absprod is not None else None
+    print("[parity] %s %s: err_row %.3e err_peak %.3e err_elem %s" %
+          (what, dt, er, ep, "-" if ee is None else "%.3e (bound %.3e)" % (ee, elem_bound(dt, k))))
+    assert er <= ROW_TOL[dt], (what, dt, "err_row", er)
+    if dt in PEAK_TOL:
+        assert ep <= PEAK_TOL[dt], (what, dt, "err_peak", ep)
+    if ee is not None:
+        assert ee <= elem_bound(dt, k), (what, dt, "err_elem", ee, elem_bound(dt, k))
+    return er, ep, ee

@@ -363,3 +363,26 @@ def test_dimensions_of_2_31_or_more_are_not_supported():
     L = B.lib()
     assert L.hs_gemv(big, 8, B.HS_F32, B.hs_schedule(4, 2), FAKE, 8, FAKE, FAKE, None, 0, None) == \
         B.HS_ERR_NOT_SUPPORTED
+
+
+def test_row_layout_rejects_overlapping_rows():
+    """A view whose rows overlap (an expanded tensor: row stride 0) would let
+    the pack kernels read past its storage; the binding refuses it before
+    any launch.  Shapes and strides as torch reports them."""
+    # torch.randn(1, 8).expand(5, 8): shape (5, 8), strides (0, 1)
+    with pytest.raises(ValueError, match="overlapping rows"):
+        B.row_layout((5, 8), (0, 1), "A")
+    # a row stride below the row length
+    with pytest.raises(ValueError, match="overlapping rows"):
+        B.row_layout((3, 8), (4, 1), "A")
+    # elements of a row not contiguous (a transposed view)
+    with pytest.raises(ValueError, match="unit stride"):
+        B.row_layout((4, 6), (1, 4), "A")
+    # contiguous, padded rows, one row (any row stride), empty
+    assert B.row_layout((5, 8), (8, 1)) == 8
+    assert B.row_layout((5, 8), (10, 1)) == 10
+    assert B.row_layout((1, 8), (0, 1)) == 8
+    assert B.row_layout((0, 8), (8, 1)) == 8
+    assert B.row_layout((3, 0), (1, 1)) == 1
+    # a single column: any row stride >= 1 addresses distinct rows
+    assert B.row_layout((4, 1), (3, 2)) == 3

@@ -4,18 +4,19 @@ oracle (GPU).
 Each case draws sizes, a schedule (p, K | p) and a dtype from a fixed seed,
 so a failure names a reproducible case.  Shapes a form does not take (the
 FP8 forms need whole 64-element contraction blocks) are recognised by
-hs_workspace_size returning SIZE_MAX and skipped.  Tolerances are those of
-tests/test_gpu_parity.py (err_row) and tests/test_gpu_nbody.py; outputs
-are NaN-poisoned, and small-integer cases must match bit for bit.
+hs_workspace_size returning SIZE_MAX and skipped.  The gates are those of
+tests/test_gpu_parity.py (err_row, err_peak and err_elem <= c k u, from
+tests/_gpu.py) and tests/test_gpu_nbody.py; outputs are NaN-poisoned, and
+small-integer cases must match bit for bit.
 """
 import numpy as np
 import pytest
 
 import oracle
-from oracle.metrics import err_row
+from oracle.metrics import err_elem
 from paper_cs_9809105_amd import binding as B
 from paper_cs_9809105_amd import inputs
-from tests._gpu import gpu_available, host, note, poisoned, to_dev
+from tests._gpu import ROW_TOL, check, gpu_available, host, note, poisoned, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -23,9 +24,8 @@ if gpu_available():
     import torch
     import paper_cs_9809105_amd as hs
 
-TOL = {"f64": 1e-12, "f32": 1e-5, "split3_bf16": 1e-5, "bf16": 1.5e-2, "f16": 3e-3,
-       "fp8_e4m3": 1e-1, "fp8_e4m3_r1": 1e-2}
-DTYPES = list(TOL)
+DTYPES = ["f64", "f32", "split3_bf16", "bf16", "f16", "fp8_e4m3", "fp8_e4m3_r1"]
+FP8_R1_ELEM = 2.0 ** -10
 
 
 def _skip_no_gpu():
@@ -90,9 +90,20 @@ def test_random_products(seed):
     if ints:   # |x| <= 4: exact in every form and every partial sum is exact
         assert np.array_equal(got[0], ref) and np.array_equal(got[1], ref)
         assert np.array_equal(got[2], rA) and np.array_equal(got[3], rB)
-    else:
+    elif dt.startswith("fp8"):
+        from oracle.metrics import err_row
         e = (err_row(got[0], ref), err_row(got[1], ref), err_row(got[2], rA), err_row(got[3], rB))
-        assert max(e) <= TOL[dt], (seed, dt, e)
+        assert max(e) <= ROW_TOL[dt], (seed, dt, e)
+        if dt == "fp8_e4m3_r1":
+            assert err_elem(got[0], ref, oracle.absprod(A64, B64)) <= FP8_R1_ELEM
+    else:
+        apC = oracle.absprod(A64, B64)
+        apA, apB = oracle.backward(np.abs(A64), np.abs(B64), np.abs(G64))
+        what = "random %d %s" % (seed, (m, n, k, p, K))
+        check(got[0], ref, dt, k, apC, what=what + " C")
+        check(got[1], ref, dt, k, apC, what=what + " C tn")
+        check(got[2], rA, dt, n, apA, what=what + " dA")
+        check(got[3], rB, dt, m, apB, what=what + " dB")
 
 
 @pytest.mark.parametrize("seed", range(16))
@@ -107,8 +118,8 @@ def test_random_gemv(seed):
     note("random gemv", seed, dt, (m, n), (p, K))
     y = hs.hs_gemv(A, x, dtype=dt, p=p, K=K)
     torch.cuda.synchronize()
-    tol = 1e-12 if dt == "f64" else 1e-5
-    assert err_row(host(y)[None, :], oracle.gemv(A64, x64)[None, :]) <= tol
+    check(host(y)[None, :], oracle.gemv(A64, x64)[None, :], dt, n,
+          oracle.gemv(np.abs(A64), np.abs(x64))[None, :], what="random gemv %d" % seed)
 
 
 def _cplx(shape, seed):
@@ -139,12 +150,15 @@ def test_random_complex(seed):
 
     def c(t):
         return t.cpu().numpy().astype(np.complex128)
-    e = (err_row(c(C), oracle.complex_gemm(Ah, Bh)),
-         err_row(c(Ct), oracle.complex_gemm(Ath.T, Bh)),
-         err_row(c(dA), oracle.complex_gemm(Gh, np.conj(Bh).T)),
-         err_row(c(dB), oracle.complex_gemm(np.conj(Ah).T, Gh)),
-         err_row(c(y)[None, :], oracle.complex_gemv(Ah, xh)[None, :]))
-    assert max(e) <= 1e-5, (seed, dt, e)
+    what = "random complex %d" % seed
+    check(c(C), oracle.complex_gemm(Ah, Bh), dt, k, oracle.complex_absprod(Ah, Bh), what=what + " C")
+    check(c(Ct), oracle.complex_gemm(Ath.T, Bh), dt, k, oracle.complex_absprod(Ath.T, Bh), what=what + " C tn")
+    check(c(dA), oracle.complex_gemm(Gh, np.conj(Bh).T), dt, n, oracle.complex_absprod(Gh, Bh.T),
+          what=what + " dA")
+    check(c(dB), oracle.complex_gemm(np.conj(Ah).T, Gh), dt, m, oracle.complex_absprod(Ah.T, Gh),
+          what=what + " dB")
+    check(c(y)[None, :], oracle.complex_gemv(Ah, xh)[None, :], "c32", k,
+          oracle.complex_absprod(Ah, xh[:, None])[:, 0][None, :], what=what + " y")
 
 
 @pytest.mark.parametrize("seed", range(16))
