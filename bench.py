@@ -100,27 +100,30 @@ def run_form(hs, torch, A, B, G, form, p, K, steps, warmup):
 
 
 def accuracy(outs, ref, n_elem=64):
-    """err_row and err_peak of the timed step's C, dA and dB on the rows the
-    CPU baseline sampled, and err_elem (|dC| over the sum of absolute
-    products) on the first ``n_elem`` of them."""
+    """err_row of the timed step's C, dA and dB on the rows the CPU baseline
+    sampled, and err_elem (|dC| over the sum of absolute products) and
+    err_term (|dC| over sqrt(k sum of squared products)) on the first
+    ``n_elem`` of them."""
     import numpy as np
     import torch
     import oracle
-    from oracle.metrics import err_elem, err_peak, err_row
+    from oracle.metrics import err_elem, err_row, err_term
     rows_m, rows_k = ref["rows_m"], ref["rows_k"]
     A64, B64, G64 = ref["A"], ref["B"], ref["G"]
-    aA, aB, aG = np.abs(A64), np.abs(B64), np.abs(G64)
     e = rows_m[:n_elem], rows_k[:n_elem]
-    absp = {"C": lambda: oracle.gemm_rows(aA, aB, e[0]),
-            "dA": lambda: oracle.grad_a_rows(aG, aB, e[0]),
-            "dB": lambda: oracle.grad_b_rows(aA, aG, e[1])}
+    # the operands of each output's sampled rows, as they multiply
+    ops = {"C": lambda: (A64[e[0]], B64), "dA": lambda: (G64[e[0]], B64.T),
+           "dB": lambda: (A64[:, e[1]].T, G64)}
     res = {}
     for name, out, rows in zip(("C", "dA", "dB"), outs, (rows_m, rows_m, rows_k)):
         got = out.index_select(0, torch.as_tensor(rows, device=out.device)).double().cpu().numpy()
         r = ref[name]
-        res[name] = {"err_row": err_row(got, r), "err_peak": err_peak(got, r),
-                     "err_elem": err_elem(got[:n_elem], r[:n_elem], absp[name]())}
-    res["rows"] = "%d sampled rows of each output (err_elem on %d of them)" % (len(rows_m), min(n_elem, len(rows_m)))
+        X, Y = ops[name]()
+        res[name] = {"err_row": err_row(got, r),
+                     "err_elem": err_elem(got[:n_elem], r[:n_elem], oracle.absprod(X, Y)),
+                     "err_term_u": err_term(got[:n_elem], r[:n_elem], oracle.sqprod(X, Y), X.shape[1]) / 2.0 ** -24}
+    res["rows"] = ("%d sampled rows of each output (err_elem, err_term in units of 2^-24 on %d of them)"
+                   % (len(rows_m), min(n_elem, len(rows_m))))
     return res
 
 
@@ -245,10 +248,12 @@ def gemv_main(args):
         cpu = {"value": nbytes * reps / t_cpu / 1e9, "unit": "GB/s", "kind": "oracle",
                "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)),
                "sample": "%d full %dx%d FP64 matrix-vector products (%.1f s)" % (reps, n, n, t_cpu)}
-        from oracle.metrics import err_elem, err_peak, err_row
+        from oracle.metrics import err_elem, err_row, err_term
         yg = y.double().cpu().numpy()[None, :]
-        acc = {"f32": {"y": {"err_row": err_row(yg, yref[None, :]), "err_peak": err_peak(yg, yref[None, :]),
-                             "err_elem": err_elem(yg, yref[None, :], oracle.gemv(abs(Ah), abs(xh))[None, :])},
+        acc = {"f32": {"y": {"err_row": err_row(yg, yref[None, :]),
+                             "err_elem": err_elem(yg, yref[None, :], oracle.gemv(abs(Ah), abs(xh))[None, :]),
+                             "err_term_u": err_term(yg, yref[None, :], oracle.gemv(Ah * Ah, xh * xh)[None, :], n)
+                             / 2.0 ** -24},
                        "rows": "all %d elements of the last timed y" % n}}
     else:
         acc = None
@@ -393,11 +398,13 @@ def complex_main(args):
         dt = time.perf_counter() - t0
         cpu = {"value": 8.0 * nrows * n * n / dt / 1e12, "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
                "sample": "%d sampled rows of C (n=%d complex, FP64 parts, %.1f s)" % (nrows, n, dt)}
-        from oracle.metrics import err_elem, err_peak, err_row
+        from oracle.metrics import err_elem, err_row, err_term
         got = C_last.index_select(0, torch.as_tensor(rows, device=C_last.device)).cpu().numpy().astype(np.complex128)
         ne = min(16, nrows)
-        acc = {form: {"C": {"err_row": err_row(got, ref), "err_peak": err_peak(got, ref),
-                            "err_elem": err_elem(got[:ne], ref[:ne], oracle.complex_absprod_rows(Ah, Bh, rows[:ne]))},
+        acc = {form: {"C": {"err_row": err_row(got, ref),
+                            "err_elem": err_elem(got[:ne], ref[:ne], oracle.complex_absprod_rows(Ah, Bh, rows[:ne])),
+                            "err_term_u": err_term(got[:ne], ref[:ne], oracle.complex_sqprod(Ah[rows[:ne]], Bh),
+                                                   2 * n) / 2.0 ** -24},
                       "rows": "%d sampled rows of the last timed C (err_elem on %d)" % (nrows, ne)}}
     else:
         acc = None

@@ -253,3 +253,19 @@ def complex_absprod_rows(A, B, rows):
     Ar, Ai, Br, Bi = np.abs(A.real), np.abs(A.imag), np.abs(B.real), np.abs(B.imag)
     return ((gemm_rows(Ar, Br, rows) + gemm_rows(Ai, Bi, rows))
             + 1j * (gemm_rows(Ar, Bi, rows) + gemm_rows(Ai, Br, rows)))
+
+
+def sqprod(A, B):
+    """sum_k a_ik^2 b_kj^2 (the squared 2-norm of the terms of each dot
+    product; the scale of err_term)."""
+    A, B = _d(A), _d(B)
+    return gemm(A * A, B * B)
+
+
+def complex_sqprod(A, B):
+    """sum of squared real terms of each part of the complex product, as
+    re + 1j im (terms as in complex_absprod)."""
+    A = np.asarray(A, np.complex128)
+    B = np.asarray(B, np.complex128)
+    Ar, Ai, Br, Bi = A.real ** 2, A.imag ** 2, B.real ** 2, B.imag ** 2
+    return (gemm(Ar, Br) + gemm(Ai, Bi)) + 1j * (gemm(Ar, Bi) + gemm(Ai, Br))

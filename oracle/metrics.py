@@ -2,10 +2,13 @@
 
 err_row  = max_r ||C_r - Chat_r||_2 / ||Chat_r||_2
            (relative error per output row; insensitive to per-row scales)
-err_peak = max_r max_j |C_rj - Chat_rj| / (||Chat_r||_2 / sqrt(n))
-           (the largest single-element error, relative to its row's rms
-           magnitude: a lone wrong element of an n-wide row moves err_row by
-           only 1/sqrt(n) of what it moves err_peak)
+err_term = max_ij |C_ij - Chat_ij| / sqrt(k sum_t a_it^2 b_tj^2)
+           (each element's error over the statistical scale of the rounding
+           errors of its k-term dot product: the sum of the rounding errors
+           of the partial sums S_t behaves like u sqrt(sum_t S_t^2), and
+           sum_t S_t^2 is of the order of k sum_t (a_it b_tj)^2; unlike a
+           per-row norm, it sees a lone wrong element at its own scale.
+           sqprod holds sum_t a_it^2 b_tj^2; complex results as for err_elem)
 err_elem = max_ij |C_ij - Chat_ij| / (|A| |B|)_ij
            (error relative to the sum of absolute products, the scale of
            every rounding-error bound of a dot product; for complex results
@@ -14,7 +17,8 @@ err_elem = max_ij |C_ij - Chat_ij| / (|A| |B|)_ij
            absprod.imag)
 
 A row whose reference is all zeros is measured in absolute terms (its
-denominator is taken as 1), and so is an element whose absprod is zero.
+denominator is taken as 1), and so is an element whose absprod or sqprod
+is zero.
 """
 import numpy as np
 
@@ -41,13 +45,16 @@ def err_row(C, ref):
     return float(np.max(num / den)) if C.size else 0.0
 
 
-def err_peak(C, ref):
-    C, ref = _rows(C, ref)
+def err_term(C, ref, sqprod, k):
+    C, ref = _promote(C, ref)
     if not C.size:
         return 0.0
-    rms = np.linalg.norm(ref, axis=1) / np.sqrt(C.shape[1])
-    rms = np.where(rms == 0, 1.0, rms)
-    return float(np.max(np.abs(C - ref).max(axis=1) / rms))
+    if np.iscomplexobj(C):
+        sq = np.asarray(sqprod, np.complex128)
+        return max(err_term(C.real, ref.real, sq.real, k), err_term(C.imag, ref.imag, sq.imag, k))
+    den = np.sqrt(max(int(k), 1) * np.asarray(sqprod, np.float64))
+    den = np.where(den == 0, 1.0, den)
+    return float(np.max(np.abs(C - ref) / den))
 
 
 def err_elem(C, ref, absprod):

@@ -48,12 +48,15 @@ def poisoned(shape, dtype, device="cuda"):
 # err_row (relative 2-norm per row): the stated tolerances of each form
 ROW_TOL = {"f64": 1e-12, "f32": 1e-5, "split3_bf16": 1e-5, "bf16": 1.5e-2, "f16": 3e-3,
            "fp8_e4m3": 1e-1, "fp8_e4m3_r1": 1e-2, "c32": 1e-5, "c32_split3_bf16": 1e-5}
-# err_peak (largest element error over its row's rms) for the FP32-accurate
-# and FP64 forms: a lone wrong element of an n-wide row moves err_row by
-# only 1/sqrt(n) of this, so the row gate alone would let it pass
-PEAK_TOL = {"f64": 1e-12, "f32": 5e-5, "split3_bf16": 5e-5, "c32": 5e-5, "c32_split3_bf16": 5e-5}
-# Element-wise bound |dC_ij| <= c k u (|A||B|)_ij, u the unit roundoff of the
-# accumulator (FP32 2^-24, FP64 2^-53), k the contraction length:
+# err_term (element error over u sqrt(k sum_t (a_t b_t)^2), the statistical
+# scale of a dot product's rounding errors) for the FP32-accurate and FP64
+# forms: 16 u.  Round-to-nearest FP32 accumulation of the workloads' inputs
+# measures 0.5 - 0.7 u; a lone wrong element is caught once its error
+# passes 16 u sqrt(k) of its own magnitude (8.6e-5 at k = 8192), where the
+# row gate needs 1e-5 sqrt(n) (9e-4 at n = 8192).
+TERM_C = {"f64": 16, "f32": 16, "split3_bf16": 16}
+# Element-wise bound |dC_ij| <= (c k + d) u (|A||B|)_ij, u the unit roundoff
+# of the accumulator (FP32 2^-24, FP64 2^-53), k the contraction length:
 #   * every product a_ik b_kj of the stored inputs enters one accumulator
 #     chain; each addition errs by less than one unit in the last place of
 #     its result (< 2u relative, also where the MFMA truncates the aligned
@@ -71,29 +74,58 @@ UNIT = {"f64": 2.0 ** -53, "f32": 2.0 ** -24, "bf16": 2.0 ** -24, "f16": 2.0 ** 
 COMPLEX_BASE = {"c32": "f32", "c32_split3_bf16": "split3_bf16"}
 
 
+def _base(dt, k):
+    """(real form, contraction of the real product) of form ``dt``."""
+    return (COMPLEX_BASE[dt], 2 * k) if dt in COMPLEX_BASE else (dt, k)
+
+
 def elem_bound(dt, k):
     """(c k + d) u of the element-wise gate for form ``dt`` and contraction ``k``."""
-    if dt in COMPLEX_BASE:
-        return elem_bound(COMPLEX_BASE[dt], 2 * k)
-    c, d = ELEM_C[dt]
-    return (c * max(int(k), 1) + d) * UNIT[dt]
+    b, kk = _base(dt, k)
+    c, d = ELEM_C[b]
+    return (c * max(int(kk), 1) + d) * UNIT[b]
 
 
-def check(got, ref, dt, k=None, absprod=None, what=""):
-    """Assert the parity gates of form ``dt``: err_row always, err_peak for
-    the FP32-accurate and FP64 forms, err_elem <= c k u when ``absprod`` (the
-    oracle's sum of absolute products of the same elements) is given.
-    Returns the measured (err_row, err_peak, err_elem)."""
-    from oracle.metrics import err_elem, err_peak, err_row
-    assert not np.isnan(np.asarray(got)).any(), (what, "NaN in the result")
+def term_bound(dt, k):
+    """The err_term gate of form ``dt`` (None: not gated)."""
+    b, _ = _base(dt, k)
+    return TERM_C[b] * UNIT[b] if b in TERM_C else None
+
+
+def check(got, ref, dt, X=None, Y=None, what="", vector=False):
+    """Assert the parity gates of form ``dt`` on a result ``got`` of the
+    product X . Y (X, Y the FP64 operands as they multiply, sampled rows of
+    X where only those rows were compared): err_row always; err_elem <=
+    (c k + d) u and, for the FP32-accurate and FP64 forms, err_term <= 16 u
+    when the operands are given.  ``vector``: got and ref are the vector
+    y = X . Y[:, 0], gated as one row.  Returns (err_row, err_term, err_elem)."""
+    import oracle
+    from oracle.metrics import err_elem, err_row, err_term
+    got, ref = np.asarray(got), np.asarray(ref)
+    assert not np.isnan(got).any(), (what, "NaN in the result")
+    ap = sq = None
+    k = None
+    if X is not None:
+        k = X.shape[1]
+        if np.iscomplexobj(X) or np.iscomplexobj(Y):
+            ap, sq = oracle.complex_absprod(X, Y), oracle.complex_sqprod(X, Y)
+        else:
+            ap, sq = oracle.absprod(X, Y), oracle.sqprod(X, Y)
+    if vector:
+        got, ref = got.reshape(1, -1), ref.reshape(1, -1)
+        if ap is not None:
+            ap, sq = ap.reshape(1, -1), sq.reshape(1, -1)
     er = err_row(got, ref)
-    ep = err_peak(got, ref)
-    ee = err_elem(got, ref, absprod) if absprod is not None else None
-    print("[parity] %s %s: err_row %.3e err_peak %.3e err_elem %s" %
-          (what, dt, er, ep, "-" if ee is None else "%.3e (bound %.3e)" % (ee, elem_bound(dt, k))))
+    ee = err_elem(got, ref, ap) if ap is not None else None
+    b, kk = _base(dt, k or 1)
+    et = err_term(got, ref, sq, kk) if sq is not None else None
+    tb = term_bound(dt, k or 1)
+    print("[parity] %s %s: err_row %.3e err_term %s err_elem %s" %
+          (what, dt, er, "-" if et is None else "%.2f u" % (et / UNIT[b]),
+           "-" if ee is None else "%.3e (bound %.3e)" % (ee, elem_bound(dt, k))))
     assert er <= ROW_TOL[dt], (what, dt, "err_row", er)
-    if dt in PEAK_TOL:
-        assert ep <= PEAK_TOL[dt], (what, dt, "err_peak", ep)
     if ee is not None:
         assert ee <= elem_bound(dt, k), (what, dt, "err_elem", ee, elem_bound(dt, k))
-    return er, ep, ee
+    if et is not None and tb is not None:
+        assert et <= tb, (what, dt, "err_term", et / UNIT[b])
+    return er, et, ee

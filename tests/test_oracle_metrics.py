@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import oracle
-from oracle.metrics import err_elem, err_peak, err_row
+from oracle.metrics import err_elem, err_row, err_term
 
 # ---------------------------------------------------------------------------
 # fixtures, with the values worked out by hand
@@ -22,9 +22,13 @@ from oracle.metrics import err_elem, err_peak, err_row
 REF = np.array([[3.0, 4.0], [6.0, 8.0], [0.6, 0.8]])
 GOT = np.array([[3.0, 4.5], [6.0, 8.0], [0.72, 0.96]])
 ERR_ROW = 0.2
-# rms of the rows: 5/sqrt2, 10/sqrt2, 1/sqrt2; largest element errors 0.5, 0, 0.16
-#   row 0: 0.5 sqrt2 / 5 = 0.14142..;  row 2: 0.16 sqrt2 = 0.22627..  <- maximum
-ERR_PEAK = 0.16 * np.sqrt(2.0)
+# err_term: errors |GOT3 - REF3| = [[0, 0.5], [0.3, 0]] over sqrt(k SQP) with
+# k = 4, SQP = [[4, 1], [9, 16]], i.e. over [[4, 2], [6, 8]]:
+# [[0, 0.25], [0.05, 0]] -> 0.25
+REF3 = np.array([[1.0, 2.5], [3.0, 4.0]])
+GOT3 = np.array([[1.0, 3.0], [3.3, 4.0]])
+SQP, K3 = np.array([[4.0, 1.0], [9.0, 16.0]]), 4
+ERR_TERM = 0.25
 
 # element errors |GOT2 - REF2| = [[0.5, 0], [0, 0.25]] over ABSP = [[4, 4], [5, 1]]
 # -> [[0.125, 0], [0, 0.25]]: err_elem = 0.25
@@ -39,6 +43,9 @@ ERR_ELEM = 0.25
 ABS_A = np.array([[1.0, -2.0], [3.0, 4.0]])
 ABS_B = np.array([[-1.0, 2.0], [0.5, -3.0]])
 ABSPROD = np.array([[2.0, 8.0], [5.0, 18.0]])
+# sum_k a^2 b^2 by hand: A^2 = [[1, 4], [9, 16]], B^2 = [[1, 4], [0.25, 9]]
+#   (0,0) 1 + 4*0.25 = 2   (0,1) 4 + 4*9 = 40   (1,0) 9 + 16*0.25 = 13   (1,1) 36 + 144 = 180
+SQPROD = np.array([[2.0, 40.0], [13.0, 180.0]])
 
 
 def test_err_row_hand_value():
@@ -53,17 +60,21 @@ def test_err_row_hand_value():
     assert err_row(np.zeros((0, 3)), np.zeros((0, 3))) == 0.0
 
 
-def test_err_peak_hand_value():
-    assert err_peak(GOT, REF) == pytest.approx(ERR_PEAK, rel=1e-12)
-    assert err_peak(REF, REF) == 0.0
-    # a lone wrong element of a wide row: err_peak sees it sqrt(n) times
-    # more strongly than err_row
-    n = 1024
+def test_err_term_hand_value():
+    assert err_term(GOT3, REF3, SQP, K3) == pytest.approx(ERR_TERM, rel=1e-12)
+    assert err_term(REF3, REF3, SQP, K3) == 0.0
+    # a lone wrong element of a wide row is seen at its own scale: a row
+    # gate dilutes it by sqrt(n)
+    n, k = 1024, 64
     ref = np.ones((1, n))
+    sq = np.full((1, n), 1.0 / k)          # k terms of size 1/k summing to 1
     got = ref.copy()
     got[0, 17] += 1e-3
-    assert err_peak(got, ref) == pytest.approx(1e-3, rel=1e-9)
+    assert err_term(got, ref, sq, k) == pytest.approx(1e-3, rel=1e-9)
     assert err_row(got, ref) == pytest.approx(1e-3 / np.sqrt(n), rel=1e-9)
+    # complex: parts against their own scales (re 0.5 / sqrt(1 * 4), im 0.3 / sqrt(1 * 1))
+    assert err_term(np.array([[1.5 + 0.3j]]), np.array([[1.0 + 0j]]), np.array([[4.0 + 1.0j]]), 1) == \
+        pytest.approx(0.3, rel=1e-12)
 
 
 def test_err_elem_hand_value():
@@ -91,6 +102,18 @@ def test_absprod_hand_value():
     assert (np.abs(C) <= got).all() and not np.array_equal(np.abs(C), got)
 
 
+def test_sqprod_hand_value():
+    got = oracle.sqprod(ABS_A, ABS_B)
+    assert np.array_equal(got, SQPROD)
+    # Cauchy-Schwarz and its converse: |A||B|^2 / k <= sum a^2 b^2 <= |A||B|^2
+    k = ABS_A.shape[1]
+    assert (ABSPROD ** 2 / k <= got).all() and (got <= ABSPROD ** 2).all()
+    # planted mistakes: the square of the product, the product of squares
+    # of one operand only
+    assert not np.array_equal(oracle.gemm(ABS_A, ABS_B) ** 2, SQPROD)
+    assert not np.array_equal(oracle.gemm(ABS_A * ABS_A, np.abs(ABS_B)), SQPROD)
+
+
 def test_complex_absprod_hand_value():
     # a = 1 - 2i, b = 3 + 0.5i:
     #   re c = 3 + 1 = 4, its scale |1||3| + |-2||0.5| = 4
@@ -100,6 +123,8 @@ def test_complex_absprod_hand_value():
     assert np.array_equal(oracle.complex_gemm(A, B), np.array([[4.0 - 5.5j]]))
     assert np.array_equal(oracle.complex_absprod(A, B), np.array([[4.0 + 6.5j]]))
     assert np.array_equal(oracle.complex_absprod_rows(A, B, [0]), np.array([[4.0 + 6.5j]]))
+    # squared terms: re 3^2 + (-2 * 0.5)^2 = 10, im 0.5^2 + (-2 * 3)^2 = 36.25
+    assert np.array_equal(oracle.complex_sqprod(A, B), np.array([[10.0 + 36.25j]]))
 
 
 # ---------------------------------------------------------------------------
@@ -130,22 +155,25 @@ def test_err_row_mutants_caught(mutant):
     assert abs(mutant(GOT, REF) - ERR_ROW) > 1e-3
 
 
-def _peak_no_sqrt(C, ref):        # row norm instead of row rms
-    return float(np.max(np.abs(C - ref).max(axis=1) / np.linalg.norm(ref, axis=1)))
+def _term_no_sqrt(C, ref, sq, k):    # k sum a^2 b^2 without the square root
+    return float(np.max(np.abs(C - ref) / (k * sq)))
 
 
-def _peak_mean(C, ref):           # mean element error instead of the largest
-    n = C.shape[1]
-    return float(np.max(np.abs(C - ref).mean(axis=1) / (np.linalg.norm(ref, axis=1) / np.sqrt(n))))
+def _term_no_k(C, ref, sq, k):       # the terms' 2-norm without sqrt(k)
+    return float(np.max(np.abs(C - ref) / np.sqrt(sq)))
 
 
-def _peak_global_rms(C, ref):     # one rms for the whole matrix
-    return float(np.abs(C - ref).max() / np.sqrt(np.mean(ref ** 2)))
+def _term_by_ref(C, ref, sq, k):     # |Chat| as the scale
+    return float(np.max(np.abs(C - ref) / np.abs(ref)))
 
 
-@pytest.mark.parametrize("mutant", [_peak_no_sqrt, _peak_mean, _peak_global_rms])
-def test_err_peak_mutants_caught(mutant):
-    assert abs(mutant(GOT, REF) - ERR_PEAK) > 1e-3
+def _term_mean(C, ref, sq, k):       # mean instead of max
+    return float(np.mean(np.abs(C - ref) / np.sqrt(k * sq)))
+
+
+@pytest.mark.parametrize("mutant", [_term_no_sqrt, _term_no_k, _term_by_ref, _term_mean])
+def test_err_term_mutants_caught(mutant):
+    assert abs(mutant(GOT3, REF3, SQP, K3) - ERR_TERM) > 1e-3
 
 
 def _elem_mean(C, ref, ap):       # mean instead of max
