@@ -1,6 +1,7 @@
 // hs_api.cpp -- host side of the C ABI declared in include/hs.h: argument
 // validation, the schedule (bases of Sec. 5.2.1), workspace planning and the
-// launch sequence pack -> main loop -> back-shift on the caller's stream.
+// launch sequence pack -> main loop (whose workgroups also collect the
+// back-shift) on the caller's stream.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -34,13 +35,6 @@ using namespace hs;
 namespace {
 
 const int kMaxP = 4096;
-// Bytes of partial planes per column phase (0: all columns in one phase).
-// 128 MB costs no measurable time at n = 8192 (two to four phases) and bounds
-// the partial workspace whatever K and N.
-#ifndef HS_PARTIAL_BUDGET
-#define HS_PARTIAL_BUDGET (128ull << 20)
-#endif
-const size_t kPartialBudget = (size_t)HS_PARTIAL_BUDGET;
 const size_t kAlign = 256;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -84,8 +78,8 @@ struct Plan {
     int p, K, Kt;
     int64_t M, N, Kd;
     OperandGeom ga, gb;
-    size_t off_a, off_b, off_w, total;
-    int64_t phase_tiles;              // column tiles per phase of the partial planes
+    size_t off_a, off_b, total;
+    int G;                            // stripes per workgroup tile (one residue class)
     int64_t a_span;                   // bytes of a workgroup's static-operand region
     size_t off_ea, off_eb;            // fp8: tile exponents of each operand
     int64_t tiles_k, tiles_ra, tiles_rb;
@@ -114,7 +108,6 @@ hs_status make_plan(int64_t M, int64_t N, int64_t Kd, hs_dtype dt, hs_schedule s
     P->M = M; P->N = N; P->Kd = Kd;
     const int BMT = mm_tile_rows(P->f.fam), BNT = mm_tile_cols(P->f.fam);
     const int CPS = mm_chunks_per_stage(P->f.fam, P->f.form);
-    if (P->K > BMT) return HS_ERR_NOT_SUPPORTED;   // K groups of >= 1 row per tile
     const int p = P->p;
     const bool fp8 = P->f.fam == FAM_FP8;
     const int CBY = fp8 ? 64 : 32;                  // chunk bytes
@@ -122,7 +115,10 @@ hs_status make_plan(int64_t M, int64_t N, int64_t Kd, hs_dtype dt, hs_schedule s
     const int64_t S_r = std::max<int64_t>(1, ceil_div(M, p));
     const int64_t S_k = std::max<int64_t>(1, ceil_div(Kd, p));
     const int64_t nch = ceil_div(ceil_div(S_k, KC), CPS) * CPS;
-    const int MS = (int)std::min<int64_t>(BMT / P->K, S_r);
+    // a workgroup tile stacks G stripe groups of MS rows, all stripes of one
+    // residue class mod K (they share every travelling block)
+    const int MS = (int)std::min<int64_t>(BMT, S_r);
+    P->G = (int)std::max<int64_t>(1, std::min<int64_t>(P->Kt, BMT / MS));
     const int NP = fp8 ? (P->f.form == 1 ? 2 : 1) : (P->f.form == 1 ? 3 : 1);
     if (fp8) {
         // every 32-row / 32-column MFMA tile and every 64-deep chunk must lie
@@ -137,7 +133,6 @@ hs_status make_plan(int64_t M, int64_t N, int64_t Kd, hs_dtype dt, hs_schedule s
     a.S_k = S_k; a.nch = nch; a.chunk_bytes = CBY; a.pieces = NP;
     a.piece_bytes = (int64_t)p * nch * MS * CBY;
     a.group_bytes = NP * a.piece_bytes;
-    a.wrap = P->K - 1;
 
     OperandGeom &b = P->gb;
     b.R = N; b.Kd = Kd; b.striped = 0; b.S_r = 0; b.grp_rows = BNT;
@@ -145,36 +140,28 @@ hs_status make_plan(int64_t M, int64_t N, int64_t Kd, hs_dtype dt, hs_schedule s
     b.S_k = S_k; b.nch = nch; b.chunk_bytes = CBY; b.pieces = NP;
     b.piece_bytes = (int64_t)p * nch * BNT * CBY;
     b.group_bytes = NP * b.piece_bytes;
-    b.wrap = 0;
 
     // grid (with padding to whole workgroup groups) must fit in 32 bits
     const int64_t nwg = (int64_t)p * a.GS * b.GS * 2 + 64;
     if (nwg > std::numeric_limits<int32_t>::max()) return HS_ERR_NOT_SUPPORTED;
     // a workgroup addresses its region of each packed operand with 32-bit
-    // offsets: K groups of the static operand, one group of the travelling
+    // offsets: G groups K GS groups apart of the static operand (fewer
+    // stripes per tile where that region would pass 4 GiB), one group of
+    // the travelling
     const int64_t kMaxPacked = (int64_t)0xFFFFFFF0;
-    P->a_span = ((int64_t)(P->K - 1) * a.GS + 1) * a.group_bytes;
+    auto span = [&](int G) { return ((int64_t)(G - 1) * P->K * a.GS + 1) * a.group_bytes; };
+    while (P->G > 1 && span(P->G) > kMaxPacked) --P->G;
+    P->a_span = span(P->G);
     if (P->a_span > kMaxPacked || b.group_bytes > kMaxPacked) return HS_ERR_NOT_SUPPORTED;
     // 32-bit indexing of the pack kernel and of the stage counter
     if (pack_units(a, 1) >= (int64_t)1 << 31 || pack_units(b, 1) >= (int64_t)1 << 31) return HS_ERR_NOT_SUPPORTED;
-    if ((int64_t)P->Kt * nch >= (int64_t)1 << 31) return HS_ERR_NOT_SUPPORTED;
+    if ((int64_t)p * nch >= (int64_t)1 << 31) return HS_ERR_NOT_SUPPORTED;
 
+    // workspace: the two packed operands (no partial planes: the collector
+    // keeps every partial in registers) and the FP8 tile exponents
     size_t off = 0;
-    P->off_a = off; off = align_up(off + (size_t)((a.n_groups + (int64_t)a.wrap * a.GS) * a.group_bytes));
+    P->off_a = off; off = align_up(off + (size_t)(a.n_groups * a.group_bytes));
     P->off_b = off; off = align_up(off + (size_t)(b.n_groups * b.group_bytes));
-    P->off_w = off;
-    // Partial planes (Sec. 6.2, cyclic mapping): the columns of C are
-    // processed in phases of phase_tiles tiles, and the K partial planes hold
-    // one phase, so their size is bounded by kPartialBudget (at least one
-    // tile wide) instead of growing as K M N.
-    P->phase_tiles = b.GS;
-    if (P->K > 1) {
-        const size_t esz = P->f.out_f64 ? 8 : 4;
-        const size_t per_tile = (size_t)P->K * M * BNT * esz;
-        if (kPartialBudget > 0 && per_tile > 0)
-            P->phase_tiles = std::max<int64_t>(1, std::min<int64_t>(b.GS, (int64_t)(kPartialBudget / per_tile)));
-        off = align_up(off + (size_t)P->K * M * std::min<int64_t>(N, P->phase_tiles * BNT) * esz);
-    }
     P->tiles_k = ceil_div(Kd, FP8_TILE);
     P->tiles_ra = ceil_div(M, FP8_TILE);
     P->tiles_rb = ceil_div(N, FP8_TILE);
@@ -274,57 +261,36 @@ hs_status run_product(const Plan &P, const Operand &X, const Operand &Y, void *o
     m.B = w + P.off_b; m.b_piece = P.gb.piece_bytes; m.b_group = P.gb.group_bytes;
     m.a_span = P.a_span;
     m.p = P.p; m.K = P.K; m.Kt = P.Kt;
-    m.MS = P.ga.grp_rows; m.GS = P.ga.GS; m.nch = P.ga.nch; m.S_r = P.ga.S_r;
+    m.MS = P.ga.grp_rows; m.G = P.G; m.GS = P.ga.GS; m.nch = P.ga.nch; m.S_r = P.ga.S_r;
     m.M = P.M; m.N = P.N; m.out_f64 = f64;
     m.a_exps = ea; m.b_exps = eb; m.a_tiles_k = P.tiles_k; m.b_tiles_k = P.tiles_k;
     m.S_k = P.ga.S_k; m.Kd = P.Kd;
-    const bool partials = P.K > 1;
-    const int64_t BNT = P.gb.grp_rows;
-    for (int64_t t0 = 0; t0 < P.gb.GS; t0 += P.phase_tiles) {
-        const int64_t nt = std::min<int64_t>(P.phase_tiles, P.gb.GS - t0);
-        const int64_t cols = std::min<int64_t>(nt * BNT, P.N - t0 * BNT);   // columns of this phase
-        m.ntile0 = t0;
-        m.n_ntiles = nt;
-        if (partials) {            // the phase's K planes: M x cols each
-            m.out = w + P.off_w;
-            m.ldo = cols;
-            m.plane = P.M * cols;
-            m.out_tile0 = t0;
-        } else {
-            m.out = out;
-            m.ldo = ldo;
-            m.plane = 0;
-            m.out_tile0 = 0;
-        }
-        {   // 32 workgroups per XCD: grp_v class members x grp_t column tiles
-            int64_t gt = 1;
-            while (gt * 2 <= 8 && gt * 2 <= nt) gt *= 2;
-            const int64_t members = (int64_t)P.Kt * P.ga.GS;
-            int64_t gv = 32 / gt;
-            while (gv > 1 && gv / 2 >= members) gv /= 2;
-            m.grp_t = gt; m.grp_v = gv;
-            m.n_tg = ceil_div(nt, gt);
-            m.n_ug = ceil_div(members, gv);
-        }
-        hipEvent_t ev0 = nullptr, ev1 = nullptr;
-        if (g_prof) {
-            if (hipEventCreate(&ev0) != hipSuccess || hipEventCreate(&ev1) != hipSuccess)
-                return HS_ERR_LAUNCH_FAILED;
-            (void)hipEventRecord(ev0, stream);
-        }
-        e = launch_mm(P.f.fam, P.f.form, m, stream);
-        if (g_prof) {
-            (void)hipEventRecord(ev1, stream);
-            g_events.push_back({ev0, ev1});
-        }
-        if (e != hipSuccess) return HS_ERR_LAUNCH_FAILED;
-        if (partials) {
-            uint8_t *c0 = (uint8_t *)out + (size_t)t0 * BNT * (f64 ? 8 : 4);
-            e = launch_backshift(f64, w + P.off_w, P.M * cols, P.K, P.M, cols, c0, ldo, stream);
-            if (e != hipSuccess) return HS_ERR_LAUNCH_FAILED;
-        }
+    m.out = out;
+    m.ldo = ldo;
+    m.n_ntiles = P.gb.GS;
+    {   // 32 workgroups per XCD: grp_v class members x grp_t column tiles
+        const int64_t nt = P.gb.GS;
+        int64_t gt = 1;
+        while (gt * 2 <= 8 && gt * 2 <= nt) gt *= 2;
+        const int64_t members = ceil_div(P.Kt, P.G) * P.ga.GS;
+        int64_t gv = 32 / gt;
+        while (gv > 1 && gv / 2 >= members) gv /= 2;
+        m.grp_t = gt; m.grp_v = gv;
+        m.n_tg = ceil_div(nt, gt);
+        m.n_ug = ceil_div(members, gv);
     }
-    return HS_OK;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (g_prof) {
+        if (hipEventCreate(&ev0) != hipSuccess || hipEventCreate(&ev1) != hipSuccess)
+            return HS_ERR_LAUNCH_FAILED;
+        (void)hipEventRecord(ev0, stream);
+    }
+    e = launch_mm(P.f.fam, P.f.form, m, stream);
+    if (g_prof) {
+        (void)hipEventRecord(ev1, stream);
+        g_events.push_back({ev0, ev1});
+    }
+    return launch_status(e);
 }
 
 hs_status check_mat(const void *p, int64_t rows, int64_t cols, int64_t ld, size_t esz) {
@@ -354,12 +320,10 @@ hs_status check_ws(const Plan &P, const void *ws, size_t ws_bytes) {
 }  // namespace
 
 // The n-body call's launch shape and workspace.  Replicas per thread (KR):
-// the largest power of two up to HS_NBODY_KR that divides K.  Two replicas
-// per thread (56 VGPRs, 8 waves per SIMD) measured fastest at n = 2^18,
-// K = 8: 3.48 T pairs/s against 3.34 (4) and 3.17 (8).
-#ifndef HS_NBODY_KR
-#define HS_NBODY_KR 2
-#endif
+// the largest power of two up to 2 that divides K.  Two replicas per thread
+// (56 VGPRs, 8 waves per SIMD) measured fastest at n = 2^18, K = 8:
+// 3.48 T pairs/s against 3.34 (4) and 3.17 (8).
+const int kNbodyKR = 2;
 hs_status nbody_plan(int64_t n, hs_dtype dtype, hs_schedule s, double eps2, NbodyArgs *a, int *kr,
                      size_t *ws) {
     if (dtype != HS_F32 && dtype != HS_F64) return HS_ERR_NOT_SUPPORTED;
@@ -377,7 +341,7 @@ hs_status nbody_plan(int64_t n, hs_dtype dtype, hs_schedule s, double eps2, Nbod
     a->Kt = r.p / r.K;
     a->S = (int)std::max<int64_t>(1, ceil_div(n, r.p));
     a->sub = (int)ceil_div(a->S, 256);
-    int k = HS_NBODY_KR;
+    int k = kNbodyKR;
     while (r.K % k != 0) k /= 2;
     *kr = k;
     a->tgroups = r.K / k;

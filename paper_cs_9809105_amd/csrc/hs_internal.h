@@ -5,13 +5,14 @@
 // dimension) by Kd contraction elements:
 //   * the static operand X (R = M) is cut into p row stripes of S_r rows
 //     (virtual processor v owns stripe v, Sec. 5.2.2); each stripe into GS
-//     groups of MS rows, zero padded;
+//     groups of MS rows, zero padded; stripe s's groups sit at positions
+//     s GS .. s GS + GS - 1;
 //   * the travelling operand Y (R = N, one row per output column) is cut into
 //     groups of BN rows (the workgroup column tile);
 //   * the contraction is cut into p blocks of S_k elements (block kb is the
 //     stripe of Y that a virtual processor holds after kb-v shifts), each
 //     padded with zeros to nch chunks of KC elements (32 or 64 bytes).
-// Packed bytes: [piece][group][kb][chunk][row in group][chunk bytes].
+// Packed bytes: [group][piece][kb][chunk][plane][row in group][16 bytes].
 // One (group, kb, chunk) is therefore a contiguous run of rows x 32 bytes,
 // which is exactly one HBM->LDS fetch of a pipeline stage.
 #pragma once
@@ -61,8 +62,6 @@ struct OperandGeom {
     int pieces;       // planes written
     int64_t piece_bytes;  // one piece of one group: p blocks x nch chunks x grp_rows x chunk_bytes
     int64_t group_bytes;  // one group, all pieces
-    int wrap;         // striped: copies of the last `wrap` stripes are stored
-                      // ahead of stripe 0 (stripe s sits at position s + wrap)
 };
 
 struct PackArgs {
@@ -92,6 +91,13 @@ enum PackEmbed {
     EMB_TRANS = 4      // the same read without the conjugation: X^T as reals
 };
 
+// One workgroup computes an output tile of G stripe groups -- stripes
+// r0, r0 + K, .., r0 + (G-1) K, all of one residue class mod K, sub-group
+// msub of each -- by BN columns, and acts as the collector of the back-shift
+// (base C = (0, 1, .., 1)): it visits the partials c^{K-1}, .., c^0 in that
+// order, computing each on the spot (partial l of stripe s is the work of
+// virtual processor s + l: travelling blocks (s + l + jK) mod p, static
+// blocks of stripe s) and accumulating it into the same registers.
 struct MainArgs {
     const uint8_t *A;        // packed static operand (layout [group][piece][block][chunk]...)
     int64_t a_piece;         // bytes between pieces inside a group
@@ -105,18 +111,16 @@ struct MainArgs {
     int64_t a_tiles_k, b_tiles_k;
     int64_t S_k;             // contraction block length (fp8 scale lookup)
     int64_t Kd;              // contraction length
-    void *out;               // partial planes (K > 1) or the result (K == 1)
+    void *out;               // the result C
     int64_t ldo;             // row stride of out (elements)
-    int64_t plane;           // elements between partial planes
     int p, K, Kt;
     int MS;                  // static-operand rows per group
+    int G;                   // stripes per workgroup tile (one residue class)
     int64_t GS;              // groups per stripe
     int64_t nch;             // chunks per contraction block
     int64_t S_r;             // stripe height
     int64_t M, N;
-    int64_t n_ntiles;        // column tiles of this launch: ntile0 .. ntile0 + n_ntiles - 1
-    int64_t ntile0;
-    int64_t out_tile0;       // column tile that lands at column 0 of out
+    int64_t n_ntiles;        // column tiles
     int out_f64;             // out element type: 1 double, 0 float
     // workgroup groups: grp_v class members x grp_t column tiles run together
     int64_t grp_v, grp_t, n_ug, n_tg;

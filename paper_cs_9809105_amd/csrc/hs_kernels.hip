@@ -8,17 +8,19 @@
 //                    in hs_internal.h; HBM bound.
 //   pack_mn_kernel   the same for an MN-major FP32 source, read as 16-byte
 //                    runs of 4 rows and transposed through LDS.
-//   mm_kernel        the hot loop: one workgroup is virtual processor v for
-//                    one (stripe sub-group, column tile).  For step j it
-//                    fetches block kb = (v + jK) mod p of the travelling
-//                    operand (base A = (0,K,..,K)) through a double-buffered
-//                    LDS ring and multiplies it, on MFMA, with the K static
-//                    blocks of stripes v, v-1, .., v-K+1 (pre-shift base
-//                    B = (0,-1,..,-1)) into K partial accumulators (the
-//                    auxiliary arrays C^l of Sec. 5.2.2).
-//   backshift_kernel the back-shift and accumulation phase (base
-//                    C = (0,1,..,1)): C[r] = c^0_r + (c^1_{r+1} + (..)), in
-//                    FP64, fixed order.
+//   mm_kernel        the hot loop: one workgroup holds an output tile of
+//                    G stripes of one residue class mod K and is the
+//                    collector of the back-shift (base C = (0,1,..,1)): it
+//                    visits the partials c^{K-1}, .., c^0 (the auxiliary
+//                    arrays C^l of Sec. 5.2.2) and forms each on the spot as
+//                    the virtual processor that owns it: K~ steps over the
+//                    travelling blocks kb = (v + jK) mod p (base
+//                    A = (0,K,..,K)), fetched through registers and a
+//                    double-buffered LDS ring, times the pre-shifted static
+//                    block (base B = (0,-1,..,-1)), on MFMA, into one
+//                    accumulator that never leaves the registers.
+//   backshift_kernel the collector of the all-pairs interaction (hs_nbody):
+//                    sums K partial planes in FP64, fixed order.
 //   gemv_kernel      y = A x with the same index map, collector form: one
 //                    wave owns a row and combines the K partial dot products
 //                    in the back-shift order (gemv_c32_kernel: complex64).
@@ -157,22 +159,10 @@ DEVI void pack_emit(const PackArgs &a, uint32_t grp, uint32_t kb, uint32_t ch, u
     const OperandGeom &g = a.g;
     const uint32_t nch = (uint32_t)g.nch, gr = (uint32_t)g.grp_rows;
     // chunk = UPR planes of 16 bytes per row: [plane][row][16 bytes]
-    // [group][piece][block][chunk][plane][row][16 bytes]; a striped group's
-    // position is shifted by the `wrap` copies ahead of stripe 0, and a group
-    // of the last `wrap` stripes is written a second time as its copy
+    // [group][piece][block][chunk][plane][row][16 bytes]
     const int64_t inner = ((int64_t)kb * nch + ch) * gr * g.chunk_bytes + ((int64_t)half * gr + rr) * 16;
-    const int64_t gpos = g.striped ? (int64_t)grp + (int64_t)g.wrap * g.GS : (int64_t)grp;
-    uint8_t *dst = (uint8_t *)a.dst + gpos * g.group_bytes + inner;
-    uint8_t *dst2 = nullptr;
-    if (g.striped && g.wrap > 0) {
-        const int64_t stripe = grp / g.GS;
-        if (stripe >= g.p - g.wrap)
-            dst2 = (uint8_t *)a.dst + ((stripe - g.p + g.wrap) * g.GS + grp % g.GS) * g.group_bytes + inner;
-    }
-    auto put = [&](int64_t at, const u32x4 &w) {
-        *(u32x4 *)(dst + at) = w;
-        if (dst2) *(u32x4 *)(dst2 + at) = w;
-    };
+    uint8_t *dst = (uint8_t *)a.dst + (int64_t)grp * g.group_bytes + inner;
+    auto put = [&](int64_t at, const u32x4 &w) { *(u32x4 *)(dst + at) = w; };
     if constexpr (KIND == PK_F64) {
         put(0, __builtin_bit_cast(u32x4, make_double2(vals_d[0], vals_d[1])));
     } else if constexpr (KIND == PK_F32) {
@@ -473,11 +463,8 @@ struct MmCfg {
     static const int TM = WM / MT, TN = WN / MT;
     static const int STAGE = A_STAGE + B_STAGE;         // one slot of the LDS ring
     static const int LPS = UA + UB;                     // DMA loads per thread per stage
-#ifndef HS_B_DIRECT
-#define HS_B_DIRECT 1
-#endif
     // B fragments straight from memory into registers (32x32 families)
-    static const bool BD = HS_B_DIRECT && FAM != FAM_F64 && FAM != FAM_FP8;
+    static const bool BD = FAM != FAM_F64 && FAM != FAM_FP8;
     static const int LDS_BYTES = 2 * (BD ? A_STAGE : STAGE);   // two slots
 };
 
@@ -699,58 +686,51 @@ void mm_kernel(MainArgs a) {
     const int wave = tid >> 6;
     const int wm = wave & 1, wn = wave >> 1;
 
-    // workgroup -> (virtual processor v, stripe sub-group msub, column tile).
-    // Workgroups are dealt to the 8 XCDs round robin; renumber them so each
-    // XCD runs a contiguous range.  Inside it, 32 consecutive workgroups (one
-    // per CU of the XCD) take G_V virtual processors of one residue class
-    // c = v mod K times G_T column tiles.  All members of a class hold the
-    // same travelling block at the same time (see the step order below), so
-    // the XCD's L2 serves each travelling tile to G_V workgroups and each
-    // static tile to G_T of them.
+    // workgroup -> (class c, stripe group sg, stripe sub-group msub, column
+    // tile).  The tile's rows are sub-group msub of the G stripes
+    // r0 + i K (i < ng), r0 = c + sg G K: all of residue class c mod K, so
+    // they need the same travelling block at every step (see the step order
+    // below).  Workgroups are dealt to the 8 XCDs round robin; renumber them
+    // so each XCD runs a contiguous range.  Inside it, 32 consecutive
+    // workgroups (one per CU of the XCD) take G_V members of one class times
+    // G_T column tiles, so the XCD's L2 serves each travelling tile to G_V
+    // workgroups and each static tile to G_T of them.
     int64_t bid = blockIdx.x;
     {
         const int64_t nwg = gridDim.x, xcd = bid % 8, per = nwg / 8, rem = nwg % 8;
         bid = xcd * per + (xcd < rem ? xcd : rem) + bid / 8;
     }
-#ifndef HS_CLASS_ORDER
-#define HS_CLASS_ORDER 1
-#endif
+    const int p = a.p, K = a.K, Kt = a.Kt, MS = a.MS, G = a.G;
     int64_t ntile, msub;
-    int v;
-    if (HS_CLASS_ORDER) {
+    int c_class, r0, ng;
+    {
         const int64_t t_lo = bid % a.grp_t;  bid /= a.grp_t;
         const int64_t u_lo = bid % a.grp_v;  bid /= a.grp_v;
         const int64_t tg = bid % a.n_tg;     bid /= a.n_tg;
         const int64_t ug = bid % a.n_ug;
-        const int c_class = (int)(bid / a.n_ug);
+        c_class = (int)(bid / a.n_ug);
         ntile = tg * a.grp_t + t_lo;
-        const int64_t u = ug * a.grp_v + u_lo;        // member of the class: (m, msub)
-        if (ntile >= a.n_ntiles || u >= (int64_t)a.Kt * a.GS) return;   // grid padding
+        const int64_t u = ug * a.grp_v + u_lo;        // member of the class: (sg, msub)
+        const int nsg = (Kt + G - 1) / G;              // stripe groups per class
+        if (ntile >= a.n_ntiles || u >= (int64_t)nsg * a.GS) return;   // grid padding
         msub = u % a.GS;
-        v = c_class + (int)(u / a.GS) * a.K;
-    } else {
-        if (bid >= (int64_t)a.p * a.GS * a.n_ntiles) return;            // grid padding
-        ntile = bid % a.n_ntiles;
-        bid /= a.n_ntiles;
-        msub = bid % a.GS;
-        v = (int)(bid / a.GS);
+        const int sg = (int)(u / a.GS);
+        r0 = c_class + sg * G * K;
+        ng = Kt - sg * G < G ? Kt - sg * G : G;        // stripes of this tile
     }
-    ntile += a.ntile0;                                  // column tile of the whole product
 
-    const int p = a.p, K = a.K, MS = a.MS;
     const int64_t nch = a.nch;
     const int spb = (int)(nch / CPS);                   // stages per contraction block
-    const int nstages = a.Kt * spb;                     // host keeps this below 2^31
+    const int nstages = p * spb;                        // host keeps this below 2^31
 
     // Each workgroup addresses its own region of the packed operands with
-    // 32-bit offsets: for the static operand the K groups of stripes v, v-1,
-    // .., v-K+1, which sit at positions v .. v+K-1 (times GS) because copies
-    // of the last K-1 stripes precede stripe 0 (so no group wraps round the
-    // ring); for the travelling operand its group of BN columns.  The host
-    // keeps each region below 4 GiB, whatever the size of the operands.
-    // Per-thread load descriptors are offsets that do not depend on the step
-    // (group, row, half-row, piece, chunk); units past the K groups (only
-    // when K * MS < BM) re-read offset 0: their tile rows are never stored.
+    // 32-bit offsets: for the static operand the G groups msub of stripes
+    // r0, r0 + K, .., which sit K GS groups apart; for the travelling operand
+    // its group of BN columns.  The host keeps each region below 4 GiB,
+    // whatever the size of the operands.  Per-thread load descriptors are
+    // offsets that do not depend on the step (group, row, half-row, piece,
+    // chunk); units past the tile's ng groups re-read offset 0: their tile
+    // rows are never stored.
     uint32_t a_off[C::UA];
 #pragma unroll
     for (int q = 0; q < C::UA; ++q) {
@@ -759,10 +739,10 @@ void mm_kernel(MainArgs a) {
         const int within = ui % (BM * C::NPL);
         const int plane = within / BM, rho = within % BM;
         const int P = slab / CPS, c = slab % CPS;
-        const int l = rho / MS, i = rho % MS;
-        a_off[q] = l < K ? (uint32_t)((int64_t)(K - 1 - l) * a.GS * a.a_group + (int64_t)P * a.a_piece +
-                                      (int64_t)c * MS * C::CB + (int64_t)(plane * MS + i) * 16)
-                         : 0u;
+        const int i = rho / MS, ir = rho % MS;
+        a_off[q] = i < ng ? (uint32_t)((int64_t)i * K * a.GS * a.a_group + (int64_t)P * a.a_piece +
+                                       (int64_t)c * MS * C::CB + (int64_t)(plane * MS + ir) * 16)
+                          : 0u;
     }
     uint32_t b_off[C::UB];
 #pragma unroll
@@ -773,32 +753,42 @@ void mm_kernel(MainArgs a) {
         const int P = slab / CPS, c = slab % CPS;
         b_off[q] = (uint32_t)((int64_t)P * a.b_piece + (int64_t)c * BN * C::CB + (int64_t)within * 16);
     }
-    const __amdgpu_buffer_rsrc_t rsA = packed_rsrc(a.A + ((int64_t)v * a.GS + msub) * a.a_group, (uint32_t)a.a_span);
+    const __amdgpu_buffer_rsrc_t rsA = packed_rsrc(a.A + ((int64_t)r0 * a.GS + msub) * a.a_group, (uint32_t)a.a_span);
     const __amdgpu_buffer_rsrc_t rsB = packed_rsrc(a.B + ntile * a.b_group, (uint32_t)a.b_group);
 
-    // Position of the next stage to fetch.  The steps of virtual processor
-    // v visit the travelling blocks kb = (v + jK) mod p, j = 0..K~-1 (base
-    // A = (0, K, .., K)), as a cycle of stride K; the cycle is entered at
-    // kb = v mod K, i.e. at step j = -(v div K) mod K~, so that every member
-    // of a residue class holds the same block at the same time.  cs counts
+    // The step order.  The collector visits the partials l = K-1, .., 0
+    // (t = K-1-l).  Partial l of stripe s is virtual processor v = s + l's
+    // work: its steps visit the travelling blocks kb = (v + jK) mod p,
+    // j = 0..K~-1 (base A = (0, K, .., K)), a cycle of stride K through the
+    // residue class (c + l) mod K, which is the same for every stripe of the
+    // tile; the cycle is entered at its smallest block (c + l) mod K, so all
+    // workgroups of class c hold the same block at the same time.  cs counts
     // the stages inside a block.  Past the last stage the position stays put,
     // so the surplus fetches re-read the last stage (never used).
-    struct Pos { int kb, cs, fetched; };
-    const int kb0 = HS_CLASS_ORDER ? v % a.K : v;
+    struct Pos { int kb, cs, j, t, n; };
+    auto advance = [&](Pos &q) {
+        if (++q.n >= nstages) return;
+        if (++q.cs < spb) return;
+        q.cs = 0;
+        if (++q.j < Kt) {                               // next step: shift by K along the ring
+            q.kb += K;
+            return;
+        }
+        q.j = 0;                                        // next partial of the collector
+        ++q.t;
+        q.kb = (c_class + K - 1 - q.t) % K;
+    };
+    const Pos start{(c_class + K - 1) % K, 0, 0, 0, 0};
     const uint32_t a_stage = (uint32_t)(MS * C::CB), b_stage = (uint32_t)(BN * C::CB);
     // first chunk of the stage at q, then advance q by one stage
     auto next_chunk = [&](Pos &q) -> uint32_t {
         // wave-uniform by construction; readfirstlane keeps the stage
         // offsets in SGPRs whatever the compiler's uniformity analysis finds
         const uint32_t ch = (uint32_t)__builtin_amdgcn_readfirstlane((int)((uint32_t)q.kb * (uint32_t)nch + (uint32_t)(q.cs * CPS)));
-        if (++q.fetched < nstages && ++q.cs == spb) {   // next step: shift by K along the ring
-            q.cs = 0;
-            q.kb += K;
-            if (q.kb >= p) q.kb -= p;
-        }
+        advance(q);
         return ch;
     };
-    Pos pa{kb0, 0, 0};
+    Pos pa = start;
     auto fetch_offsets = [&](uint32_t &ach, uint32_t &bch) {
         const uint32_t ch = next_chunk(pa);
         ach = ch * a_stage;
@@ -810,14 +800,15 @@ void mm_kernel(MainArgs a) {
     // scale tile (the host checks the alignment), so each scale is uniform
     // across the wave: 127 - e for q0, 127 - e - e1 for q1.
     int sa[CPS][C::NP][C::TM], sb[CPS][C::NP][C::TN];
-    int kbc = HS_CLASS_ORDER ? v % a.K : v, csc = 0;    // stage being multiplied
+    Pos pc = start;                                     // stage being multiplied
     int tra[C::TM], trb[C::TN];
     if constexpr (FAM == FAM_FP8) {
 #pragma unroll
         for (int mi = 0; mi < C::TM; ++mi) {
             const int rho0 = wm * C::WM + mi * 32;
-            const int l = rho0 / MS, i0 = rho0 % MS;
-            int64_t row0 = (int64_t)((v - l + p) % p) * a.S_r + msub * MS + i0;
+            const int i = rho0 / MS, i0 = rho0 % MS;
+            // rows of the groups past ng are never stored: any valid scale
+            int64_t row0 = (int64_t)(r0 + (i < ng ? i : 0) * K) * a.S_r + msub * MS + i0;
             row0 = row0 < a.M ? row0 : a.M - 1;
             tra[mi] = (int)(row0 / FP8_TILE);
         }
@@ -835,7 +826,7 @@ void mm_kernel(MainArgs a) {
             cint *eb = (cint *)a.b_exps;
 #pragma unroll
             for (int c = 0; c < CPS; ++c) {
-                int64_t kk = (int64_t)kbc * a.S_k + (int64_t)(csc * CPS + c) * 64;
+                int64_t kk = (int64_t)pc.kb * a.S_k + (int64_t)(pc.cs * CPS + c) * 64;
                 kk = kk < a.Kd ? kk : a.Kd - 1;         // padding chunks hold zeros
                 const int tc = __builtin_amdgcn_readfirstlane((int)(kk / FP8_TILE));
 #pragma unroll
@@ -853,11 +844,7 @@ void mm_kernel(MainArgs a) {
                     if constexpr (C::NP == 2) sb[c][1][ni] = 127 - e - e1;
                 }
             }
-            if (++csc == spb) {
-                csc = 0;
-                kbc += K;
-                if (kbc >= p) kbc -= p;
-            }
+            advance(pc);
         }
     };
 
@@ -872,7 +859,7 @@ void mm_kernel(MainArgs a) {
         // The travelling operand skips LDS: each wave loads its own MFMA
         // fragments of B (the packed layout already is the fragment layout:
         // 32 lanes read 512 contiguous bytes of one plane) one stage ahead,
-        // into one of two register sets.  Only the K static blocks go
+        // into one of two register sets.  Only the static blocks go
         // through LDS (two slots, loaded two stages ahead, written one
         // stage ahead, one barrier per stage), which halves the LDS writes
         // and cuts the LDS reads by a third.
@@ -891,15 +878,15 @@ void mm_kernel(MainArgs a) {
                         bq[c][P][ni] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(
                             rsB, (int)(b_lane + ni * 32 * 16), (int)(bst + P * b_piece + c * BN * C::CB), 0));
         };
-        u32x4 r0[C::UA], r1[C::UA];
+        u32x4 r0s[C::UA], r1s[C::UA];
         BQ q0, q1;
-        Pos pb{kb0, 0, 0};
+        Pos pb = start;
         fetch_offsets(ach, bch);
-        stage_load_a<C::UA>(r0, rsA, a_off, ach);
+        stage_load_a<C::UA>(r0s, rsA, a_off, ach);
         fetch_offsets(ach, bch);
-        stage_load_a<C::UA>(r1, rsA, a_off, ach);
+        stage_load_a<C::UA>(r1s, rsA, a_off, ach);
         load_b(q0, next_chunk(pb));
-        stage_store_a<C::UA, C::NT>(r0, ring, tid);
+        stage_store_a<C::UA, C::NT>(r0s, ring, tid);
         __syncthreads();
 #define HS_PIPE_STEP(RLOAD, RSTORE, QUSE, QLOAD)                                               \
     {                                                                                          \
@@ -914,8 +901,8 @@ void mm_kernel(MainArgs a) {
         if (++s >= nstages) break;                                                             \
     }
         for (int s = 0; s < nstages;) {
-            HS_PIPE_STEP(r0, r1, q0, q1)
-            HS_PIPE_STEP(r1, r0, q1, q0)
+            HS_PIPE_STEP(r0s, r1s, q0, q1)
+            HS_PIPE_STEP(r1s, r0s, q1, q0)
         }
 #undef HS_PIPE_STEP
     } else {
@@ -923,12 +910,12 @@ void mm_kernel(MainArgs a) {
         // s + 2 are issued at the top of stage s into one of two register
         // sets; the LDS image of stage s + 1 is written into the other slot
         // at the top of stage s, and one barrier closes each stage.
-        u32x4 r0[C::LPS], r1[C::LPS];
+        u32x4 r0s[C::LPS], r1s[C::LPS];
         fetch_offsets(ach, bch);
-        stage_load<C::UA, C::UB>(r0, rsA, rsB, a_off, b_off, ach, bch);
+        stage_load<C::UA, C::UB>(r0s, rsA, rsB, a_off, b_off, ach, bch);
         fetch_offsets(ach, bch);
-        stage_load<C::UA, C::UB>(r1, rsA, rsB, a_off, b_off, ach, bch);
-        stage_store<C::UA, C::UB, C::A_STAGE, C::NT>(r0, ring, tid);
+        stage_load<C::UA, C::UB>(r1s, rsA, rsB, a_off, b_off, ach, bch);
+        stage_store<C::UA, C::UB, C::A_STAGE, C::NT>(r0s, ring, tid);
         __syncthreads();
 #define HS_PIPE_STEP(RLOAD, RSTORE)                                                            \
     {                                                                                          \
@@ -945,14 +932,15 @@ void mm_kernel(MainArgs a) {
         if (++s >= nstages) break;                                                             \
     }
         for (int s = 0; s < nstages;) {
-            HS_PIPE_STEP(r0, r1)
-            HS_PIPE_STEP(r1, r0)
+            HS_PIPE_STEP(r0s, r1s)
+            HS_PIPE_STEP(r1s, r0s)
         }
 #undef HS_PIPE_STEP
     }
 
-    // epilogue: partial l of the tile row rho goes to output stripe (v - l).
-    // One tile row at a time (row index computed once, then its columns).
+    // epilogue: the collector has absorbed every partial; tile row rho is
+    // row msub MS + (rho mod MS) of stripe r0 + (rho / MS) K.  One tile row
+    // at a time (row index computed once, then its columns).
     const int64_t S_r = a.S_r;
     constexpr int NE = (int)(sizeof(Acc) / sizeof(acc[0][0][0]));
 #pragma unroll
@@ -964,13 +952,12 @@ void mm_kernel(MainArgs a) {
                 rho = wm * C::WM + mi * 16 + 4 * e + (lane >> 4);
             else                               // 32x32 f32 accumulators
                 rho = wm * C::WM + mi * 32 + (e >> 2) * 8 + (lane >> 5) * 4 + (e & 3);
-            const int l = rho / MS, i = rho % MS;
-            const int64_t within = msub * MS + i;
-            const int64_t row = (int64_t)((v - l + p) % p) * S_r + within;
-            const bool rok = l < K && within < S_r && row < a.M;
-            const int64_t obase = (int64_t)l * a.plane + row * a.ldo + (ntile - a.out_tile0) * BN + wn * C::WN +
-                                  (FAM == FAM_F64 ? (lane & 15) : (lane & 31));
+            const int i = rho / MS, ir = rho % MS;
+            const int64_t within = msub * MS + ir;
+            const int64_t row = (int64_t)(r0 + i * K) * S_r + within;
+            const bool rok = i < ng && within < S_r && row < a.M;
             const int64_t cbase = ntile * BN + wn * C::WN + (FAM == FAM_F64 ? (lane & 15) : (lane & 31));
+            const int64_t obase = row * a.ldo + cbase;
 #pragma unroll
             for (int ni = 0; ni < C::TN; ++ni) {
                 const bool ok = rok && cbase + ni * C::MT < a.N;
@@ -1229,29 +1216,15 @@ int mm_chunks_per_stage(int fam, int form) {
     return form == 1 ? 1 : 2;
 }
 
+// 8 waves (2 per SIMD) for the 256 x 256 tiles, 4 for FP64's 64 x 64.
 hipError_t launch_mm(int fam, int form, const MainArgs &a, hipStream_t st) {
-#ifndef HS_WAVES_F32
-#define HS_WAVES_F32 8
-#endif
-#ifndef HS_WAVES_B16
-#define HS_WAVES_B16 8
-#endif
-#ifndef HS_WAVES_SPLIT
-#define HS_WAVES_SPLIT 8
-#endif
     if (fam == FAM_F64) return launch_mm_t<FAM_F64, 0, 64, 64, 4, 4>(a, st);
-    if (fam == FAM_F32) return launch_mm_t<FAM_F32, 0, 256, 256, 2, HS_WAVES_F32>(a, st);
-    if (fam == FAM_F16) return launch_mm_t<FAM_F16, 0, 256, 256, 2, HS_WAVES_B16>(a, st);
-    if (fam == FAM_BF16 && form == 0) return launch_mm_t<FAM_BF16, 0, 256, 256, 2, HS_WAVES_B16>(a, st);
-    if (fam == FAM_BF16 && form == 1) return launch_mm_t<FAM_BF16, 1, 256, 256, 1, HS_WAVES_SPLIT>(a, st);
-#ifndef HS_WAVES_FP8
-#define HS_WAVES_FP8 8
-#endif
-#ifndef HS_WAVES_FP8R
-#define HS_WAVES_FP8R 8
-#endif
-    if (fam == FAM_FP8 && form == 0) return launch_mm_t<FAM_FP8, 0, 256, 256, 2, HS_WAVES_FP8>(a, st);
-    if (fam == FAM_FP8 && form == 1) return launch_mm_t<FAM_FP8, 1, 256, 256, 1, HS_WAVES_FP8R>(a, st);
+    if (fam == FAM_F32) return launch_mm_t<FAM_F32, 0, 256, 256, 2, 8>(a, st);
+    if (fam == FAM_F16) return launch_mm_t<FAM_F16, 0, 256, 256, 2, 8>(a, st);
+    if (fam == FAM_BF16 && form == 0) return launch_mm_t<FAM_BF16, 0, 256, 256, 2, 8>(a, st);
+    if (fam == FAM_BF16 && form == 1) return launch_mm_t<FAM_BF16, 1, 256, 256, 1, 8>(a, st);
+    if (fam == FAM_FP8 && form == 0) return launch_mm_t<FAM_FP8, 0, 256, 256, 2, 8>(a, st);
+    if (fam == FAM_FP8 && form == 1) return launch_mm_t<FAM_FP8, 1, 256, 256, 1, 8>(a, st);
     return hipErrorInvalidValue;
 }
 

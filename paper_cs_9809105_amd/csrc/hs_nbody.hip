@@ -169,19 +169,13 @@ hipError_t launch_nbody(int f64, const void *bodies, void *out, const NbodyArgs 
     const dim3 grid((unsigned)nwg), block(256);
 #define HS_NB(T, R) \
     hipLaunchKernelGGL((nbody_kernel<T, R>), grid, block, 0, st, (const T *)bodies, (T *)out, a)
+    // kr: replicas per thread, 2 (K even) or 1 (K odd)
     if (f64) {
-        switch (kr) {
-            case 4: HS_NB(double, 4); break;
-            case 2: HS_NB(double, 2); break;
-            default: HS_NB(double, 1); break;
-        }
+        if (kr == 2) HS_NB(double, 2);
+        else HS_NB(double, 1);
     } else {
-        switch (kr) {
-            case 8: HS_NB(float, 8); break;
-            case 4: HS_NB(float, 4); break;
-            case 2: HS_NB(float, 2); break;
-            default: HS_NB(float, 1); break;
-        }
+        if (kr == 2) HS_NB(float, 2);
+        else HS_NB(float, 1);
     }
 #undef HS_NB
     return hipGetLastError();

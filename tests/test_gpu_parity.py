@@ -695,15 +695,15 @@ def test_complex_autograd():
 
 
 @pytest.mark.parametrize("dt", ["f32", "split3_bf16"])
-def test_many_column_phases(dt):
-    """M = 16384 with K = 8: each column tile's 8 partial planes take 128 MB,
-    so every 256-column tile is a phase of its own (8 phases, the last one
-    ragged), each back-shifted before the next reuses the planes."""
+def test_tall_product_k8(dt):
+    """M = 16384, p = 64, K = 8: stripes of 256 rows, one per tile, eight
+    partials per output tile collected in registers; a ragged last column
+    tile."""
     _skip_no_gpu()
     m, k, n, p, K = 16384, 256, 2000, 64, 8
     A, A64 = to_dev(inputs.normal((m, k), seed=1101), dt)
     B, B64 = to_dev(inputs.normal((k, n), seed=1102), dt)
-    note("column phases", dt)
+    note("tall product K=8", dt)
     C = hs.hs_gemm(A, B, dtype=dt, p=p, K=K, out=poisoned((m, n), torch.float32))
     torch.cuda.synchronize()
     got = host(C)
