@@ -17,20 +17,23 @@
  *
  * This is Algorithm HYPER-SYSTOLIC applied to C^T = B^T A^T (the paper moves
  * A and keeps columns; here rows are kept and B moves).  The "cshift" of a
- * stripe is the order in which its tiles are fetched from HBM into a
- * double-buffered LDS ring; the K auxiliary arrays C^l are K partial
- * accumulators; the back-shift is a fixed-order reduction.  Each virtual
- * processor enters its cycle of K~ steps (stride K) at block v mod K rather
- * than at block v, so that all processors of a residue class hold the same
- * travelling block at the same time and share it in cache; every processor
- * still forms exactly the block products listed above.
+ * stripe is the order in which its tiles are fetched from HBM into registers
+ * and a double-buffered LDS ring.  The back-shift is done by a collector:
+ * the workgroup that owns an output tile of stripe r visits the virtual
+ * processors r + K - 1, .., r (base C reversed), forms each one's partial
+ * c^l on the spot and accumulates it into the same registers, so the K
+ * auxiliary arrays C^l never exist in memory.  Each virtual processor enters
+ * its cycle of K~ steps (stride K) at block v mod K rather than at block v,
+ * so that all processors of a residue class hold the same travelling block
+ * at the same time and share it in cache; every processor still forms
+ * exactly the block products listed above.
  *
  * Conventions for every entry point
  *  - All matrices are dense and row-major; a leading dimension (ld*) is the
  *    element distance between consecutive rows and must be >= the row length.
- *  - Every pointer except `ws` and the optional outputs of the backward call
- *    is a DEVICE pointer owned by the caller.  The library never allocates
- *    or frees device memory and never synchronises the stream: work is
+ *  - Every pointer is a DEVICE pointer owned by the caller (the outputs of
+ *    the backward call may be NULL).  The library never allocates or frees
+ *    device memory and never synchronises the stream: work is
  *    enqueued on `stream` (a hipStream_t; NULL means the null stream) and
  *    completes asynchronously.  Device faults surface at the caller's next
  *    synchronisation.
@@ -73,8 +76,8 @@ extern "C" {
  *  HS_F16          in f16,  out f32.  FP16 MFMA, FP32 accumulation.
  *  HS_SPLIT3_BF16  in f32,  out f32.  a = a0 + a1 + a2 with bf16 pieces
  *                  (round-to-nearest-even, exact residuals); the six products
- *                  a_i b_j with i + j <= 2 on BF16 MFMA, FP32 accumulation,
- *                  partial results summed in FP64.
+ *                  a_i b_j with i + j <= 2 on BF16 MFMA, smallest first, one
+ *                  FP32 accumulator per output element.
  *  HS_FP8_E4M3     in f32,  out f32.  a ~= q0 / s with q0 = e4m3(a s) and a
  *                  power-of-two s per 128 x 128 tile of the operand; one
  *                  FP8 MFMA product with hardware block scales.
@@ -115,7 +118,9 @@ typedef enum {
                                        dimension of 2^31 or more, or one
                                        workgroup's packed region above 4 GiB) */
     HS_ERR_WORKSPACE_TOO_SMALL = 3, /* ws_bytes < hs_workspace_size(...) */
-    HS_ERR_LAUNCH_FAILED = 4        /* the HIP runtime rejected a launch */
+    HS_ERR_LAUNCH_FAILED = 4,       /* the HIP runtime rejected a launch */
+    HS_ERR_EXCEEDS_SCRATCH = 5      /* hs_gemm_noalloc: the call needs more
+                                       workspace than the static scratch holds */
 } hs_status;
 
 /* Which call a workspace is sized for. */
@@ -229,6 +234,27 @@ hs_status hs_gemm_backward(int64_t m, int64_t n, int64_t k, hs_dtype dtype, hs_s
  * (K n 4 values; none for K == 1). */
 hs_status hs_nbody(int64_t n, hs_dtype dtype, hs_schedule s, const void *bodies, double eps2, void *out,
                    void *ws, size_t ws_bytes, void *stream);
+
+/* Bytes of the static scratch array of hs_gemm_noalloc (per device). */
+#define HS_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/* hs_gemm without a workspace argument, for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, harnesses
+ * that forbid allocation): the same product, kernels and results (bit for
+ * bit) as hs_gemm, with the workspace taken from a scratch array of
+ * HS_NOALLOC_SCRATCH_BYTES that the library's code object holds on every
+ * device it runs on, for the life of the process.  Neither this call nor
+ * anything it calls allocates or frees device memory.
+ * Arguments as for hs_gemm.  Returns HS_ERR_EXCEEDS_SCRATCH, before any
+ * launch, when hs_workspace_size(HS_OP_GEMM, m, n, k, dtype, s) exceeds
+ * HS_NOALLOC_SCRATCH_BYTES (for instance split-BF16 beyond about
+ * m = n = k = 2300, FP32 beyond about 2800), and HS_ERR_LAUNCH_FAILED if the
+ * runtime cannot give the scratch array's device address.  All calls on one
+ * device share its scratch array: calls that overlap in time on one device
+ * race and must be ordered by the caller (one stream, or events). */
+hs_status hs_gemm_noalloc(int64_t m, int64_t n, int64_t k, hs_dtype dtype, hs_schedule s,
+                          const void *A, int64_t lda, const void *B, int64_t ldb,
+                          void *C, int64_t ldc, void *stream);
 
 /* Kernel timing for measurement.  Between hs_profile_begin() and
  * hs_profile_end(), every launch of the main kernel of any call made from

@@ -18,7 +18,9 @@ DTYPES = {"f64": HS_F64, "f32": HS_F32, "bf16": HS_BF16, "f16": HS_F16,
           "split3_bf16": HS_SPLIT3_BF16, "fp8_e4m3": HS_FP8_E4M3, "fp8_e4m3_r1": HS_FP8_E4M3_R1,
           "c32": HS_C32, "c32_split3_bf16": HS_C32_SPLIT3_BF16}
 # hs_status
-HS_OK, HS_ERR_INVALID_VALUE, HS_ERR_NOT_SUPPORTED, HS_ERR_WORKSPACE_TOO_SMALL, HS_ERR_LAUNCH_FAILED = range(5)
+(HS_OK, HS_ERR_INVALID_VALUE, HS_ERR_NOT_SUPPORTED, HS_ERR_WORKSPACE_TOO_SMALL, HS_ERR_LAUNCH_FAILED,
+ HS_ERR_EXCEEDS_SCRATCH) = range(6)
+HS_NOALLOC_SCRATCH_BYTES = 64 << 20
 # hs_op
 HS_OP_GEMM, HS_OP_GEMM_TN, HS_OP_GEMV, HS_OP_BACKWARD, HS_OP_NBODY = range(5)
 SIZE_MAX = ctypes.c_size_t(-1).value
@@ -59,6 +61,8 @@ def lib():
     L.hs_gemm.restype = ctypes.c_int
     L.hs_gemm_tn.argtypes = mm
     L.hs_gemm_tn.restype = ctypes.c_int
+    L.hs_gemm_noalloc.argtypes = [i64, i64, i64, ctypes.c_int, hs_schedule, vp, i64, vp, i64, vp, i64, vp]
+    L.hs_gemm_noalloc.restype = ctypes.c_int
     L.hs_gemv.argtypes = [i64, i64, ctypes.c_int, hs_schedule, vp, i64, vp, vp, vp, sz, vp]
     L.hs_gemv.restype = ctypes.c_int
     L.hs_gemm_backward.argtypes = [i64, i64, i64, ctypes.c_int, hs_schedule, vp, i64, vp, i64,
@@ -217,6 +221,23 @@ def hs_gemm(A, B, dtype="f32", p=1, K=0, out=None, stream=None):
                            row_layout((m, n), C.stride()), ws.data_ptr() if ws is not None else None, nb,
                            _stream(stream))
     _check(st, "hs_gemm")
+    return C
+
+
+def hs_gemm_noalloc(A, B, out, dtype="f32", p=1, K=0, stream=None):
+    """C = A . B into ``out`` without any device allocation (the library's
+    static scratch array is the workspace)."""
+    dt = _dt(dtype)
+    a, lda = _mat(A, "A", dt)
+    b, ldb = _mat(B, "B", dt)
+    m, k = A.shape
+    k2, n = B.shape
+    if k != k2:
+        raise ValueError("inner dimensions differ: %d vs %d" % (k, k2))
+    C = _new_out((m, n), dt, A.device, out, "out")
+    st = lib().hs_gemm_noalloc(m, n, k, dt, hs_schedule(p, K), a, lda, b, ldb, C.data_ptr(),
+                               row_layout((m, n), C.stride()), _stream(stream))
+    _check(st, "hs_gemm_noalloc")
     return C
 
 

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhs.so")
 SOURCES = [os.path.join(CSRC, "hs_kernels.hip"), os.path.join(CSRC, "hs_nbody.hip"),
-           os.path.join(CSRC, "hs_api.cpp")]
+           os.path.join(CSRC, "hs_api.cpp"), os.path.join(CSRC, "hs_noalloc.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

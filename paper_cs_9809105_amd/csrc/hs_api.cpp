@@ -360,6 +360,8 @@ const char *hs_status_string(hs_status s) {
         case HS_ERR_NOT_SUPPORTED: return "HS_ERR_NOT_SUPPORTED: dtype or size not supported for this call";
         case HS_ERR_WORKSPACE_TOO_SMALL: return "HS_ERR_WORKSPACE_TOO_SMALL: workspace smaller than hs_workspace_size()";
         case HS_ERR_LAUNCH_FAILED: return "HS_ERR_LAUNCH_FAILED: the HIP runtime rejected a launch";
+        case HS_ERR_EXCEEDS_SCRATCH:
+            return "HS_ERR_EXCEEDS_SCRATCH: the call needs more workspace than hs_gemm_noalloc's static scratch holds";
     }
     return "unknown hs_status";
 }

@@ -42,7 +42,7 @@ def test_binding_names_match_abi():
 
 
 def test_status_strings():
-    for s in range(5):
+    for s in range(6):
         assert B.hs_status_string(s).startswith("HS_")
     assert B.hs_status_string(99) == "unknown hs_status"
 
@@ -390,3 +390,19 @@ def test_row_layout_rejects_overlapping_rows():
     assert B.row_layout((3, 0), (1, 1)) == 1
     # a single column: any row stride >= 1 addresses distinct rows
     assert B.row_layout((4, 1), (3, 2)) == 3
+
+
+def test_noalloc_rejects_before_any_launch():
+    """hs_gemm_noalloc refuses a call whose workspace exceeds its static
+    scratch (and keeps hs_gemm's status for invalid arguments) before it
+    touches the device."""
+    L = B.lib()
+    s = B.hs_schedule(8, 2)
+    assert B.hs_workspace_size(B.HS_OP_GEMM, 4096, 4096, 4096, "split3_bf16", 8, 2) > B.HS_NOALLOC_SCRATCH_BYTES
+    assert L.hs_gemm_noalloc(4096, 4096, 4096, B.HS_SPLIT3_BF16, s, FAKE, 4096, FAKE, 4096, FAKE, 4096,
+                             None) == B.HS_ERR_EXCEEDS_SCRATCH
+    assert L.hs_gemm_noalloc(8, 8, 8, B.HS_F32, B.hs_schedule(4, 3), FAKE, 8, FAKE, 8, FAKE, 8,
+                             None) == B.HS_ERR_INVALID_VALUE
+    assert L.hs_gemm_noalloc(8, 8, 8, 99, s, FAKE, 8, FAKE, 8, FAKE, 8, None) == B.HS_ERR_NOT_SUPPORTED
+    assert L.hs_gemm_noalloc(8, 8, 8, B.HS_F32, s, FAKE, 4, FAKE, 8, FAKE, 8, None) == B.HS_ERR_INVALID_VALUE
+    assert B.hs_status_string(B.HS_ERR_EXCEEDS_SCRATCH).startswith("HS_ERR_EXCEEDS_SCRATCH")
