@@ -443,13 +443,16 @@ def test_split3_pieces_reconstruct_exactly_backward():
 
 @pytest.mark.parametrize("dt", FP8)
 @pytest.mark.parametrize("tn", [False, True])
-def test_fp8_quantisation_bit_exact(dt, tn):
+@pytest.mark.parametrize("mkp", [(256, 384, 2), (254, 256, 4)])
+def test_fp8_quantisation_bit_exact(dt, tn, mkp):
     """A . I and I . B return the dequantised operand exactly (products with
-    an exact 1 and at most one nonzero term per element)."""
+    an exact 1 and at most one nonzero term per element).  m = 254: ragged
+    scale tiles and, read along A's columns (tn), a line length that is not
+    a whole number of 16-byte units."""
     _skip_no_gpu()
     from oracle import precision as P
     refine = dt == "fp8_e4m3_r1"
-    m, k, p = 256, 384, 2
+    m, k, p = mkp
     A, Af = to_dev(inputs.row_scaled((k, m) if tn else (m, k), seed=911), dt)
     I_k, _ = to_dev(np.eye(k), dt)
     note("fp8 quantisation, static side", dt, tn)
@@ -461,6 +464,48 @@ def test_fp8_quantisation_bit_exact(dt, tn):
     note("fp8 quantisation, travelling side", dt, tn)
     C2 = (hs.hs_gemm_tn if tn else hs.hs_gemm)(I_m, B, dtype=dt, p=p)
     assert np.array_equal(host(C2), P.fp8_dequantized(Bf, refine))
+
+
+@pytest.mark.parametrize("dt", FP8)
+def test_fp8_quantisation_ties_bit_exact(dt):
+    """Every tie of the e4m3 rounding: each 128 x 128 scale tile holds 448
+    (so its scale is 2^0) and every midpoint between neighbouring e4m3
+    values, both signs, subnormal ones included; A . I must return the
+    oracle's round-to-nearest-even dequantisation bit for bit."""
+    _skip_no_gpu()
+    from oracle import precision as P
+    refine = dt == "fp8_e4m3_r1"
+    vals = P.e4m3_table()
+    mids = 0.5 * (vals[:-1] + vals[1:])
+    special = np.concatenate([[448.0], mids, -mids, -vals[:8]])
+    A = inputs.uniform((256, 256), seed=915) * 400.0
+    for r0 in (0, 128):
+        for c0 in (0, 128):
+            t = A[r0:r0 + 128, c0:c0 + 128].reshape(-1)
+            t[:len(special)] = special
+            A[r0:r0 + 128, c0:c0 + 128] = t.reshape(128, 128)
+    Ad, Af = to_dev(A, dt)
+    I, _ = to_dev(np.eye(256), dt)
+    note("fp8 ties", dt)
+    C = hs.hs_gemm(Ad, I, dtype=dt, p=2)
+    assert np.array_equal(host(C), P.fp8_dequantized(Af, refine))
+
+
+@pytest.mark.parametrize("dt", FP8)
+def test_fp8_quantisation_unaligned_rows(dt):
+    """Operands whose rows are not 16-byte aligned (a view with row stride
+    259 floats, starting one float in): the scale pass and the pack read
+    them element by element; the quantisation is still bit-exact."""
+    _skip_no_gpu()
+    from oracle import precision as P
+    refine = dt == "fp8_e4m3_r1"
+    m, k = 224, 192
+    big, big64 = to_dev(inputs.row_scaled((m, 259), seed=914), dt)
+    A, Af = big[:, 1:1 + k], big64[:, 1:1 + k]
+    I_k, _ = to_dev(np.eye(k), dt)
+    note("fp8 quantisation, unaligned rows", dt)
+    C = hs.hs_gemm(A, I_k, dtype=dt, p=1)
+    assert np.array_equal(host(C), P.fp8_dequantized(np.ascontiguousarray(Af), refine))
 
 
 @pytest.mark.parametrize("dt", FP8)
