@@ -408,26 +408,82 @@ def _pow2_diag(n, seed):
     return np.diag(d), d
 
 
-@pytest.mark.parametrize("tn", [False, True])
-def test_split3_pieces_reconstruct_exactly(tn):
+# Split products on contiguous sources, whose pieces the pack kernels form
+# from 16-byte loads (whole 8-element units), and on the same values as
+# views with odd row strides (element loads): three stripes per tile
+# (640 x 512 x 384), ragged rows and columns, K = p, K = 1.
+PACK_LOAD_CASES = [(640, 512, 384, 8, 2), (250, 300, 512, 4, 4), (1024, 1024, 1024, 16, 16), (77, 45, 64, 4, 1),
+                (768, 768, 768, 3, 1), (512, 1024, 2048, 8, 4)]
+
+
+def _strided(x64, dt, pad=1):
+    """The same values as a view whose rows are cols + pad floats apart (not
+    16-byte aligned: the pack kernels then read element by element)."""
+    r, c = x64.shape
+    big = np.zeros((r, c + pad))
+    big[:, :c] = x64
+    t, _ = to_dev(big, dt)
+    return t[:, :c]
+
+
+@pytest.mark.parametrize("case", PACK_LOAD_CASES)
+def test_split_pack_load_paths(case):
+    """The split form on contiguous sources against the oracle, and bit for
+    bit against the same values read through odd row strides, for C = A.B,
+    A^T.B and the backward pair (both source orientations of both
+    operands)."""
     _skip_no_gpu()
-    m, k, p = 200, 320, 4
+    dt = "split3_bf16"
+    m, n, k, p, K = case
+    A, A64 = to_dev(inputs.row_scaled((m, k), seed=1601), dt)
+    At, At64 = to_dev(np.ascontiguousarray(A64.T), dt)
+    B_, B64 = to_dev(inputs.row_scaled((k, n), seed=1602), dt)
+    G, G64 = to_dev(inputs.normal((m, n), seed=1603), dt)
+    Av, Atv, Bv, Gv = _strided(A64, dt), _strided(At64, dt, 3), _strided(B64, dt), _strided(G64, dt, 2)
+    note("split contiguous", case)
+    C = hs.hs_gemm(A, B_, dtype=dt, p=p, K=K)
+    Ct = hs.hs_gemm_tn(At, B_, dtype=dt, p=p, K=K)
+    dA, dB = hs.hs_gemm_backward(A, B_, G, dtype=dt, p=p, K=K)
+    note("split strided", case)
+    Cp = hs.hs_gemm(Av, Bv, dtype=dt, p=p, K=K)
+    Ctp = hs.hs_gemm_tn(Atv, Bv, dtype=dt, p=p, K=K)
+    dAp, dBp = hs.hs_gemm_backward(Av, Bv, Gv, dtype=dt, p=p, K=K)
+    torch.cuda.synchronize()
+    for x, y in ((C, Cp), (Ct, Ctp), (dA, dAp), (dB, dBp)):
+        assert torch.equal(x, y)
+    ref = oracle.gemm(A64, B64)
+    check(host(C), ref, dt, A64, B64, what="pack paths C %s" % (case,))
+    check(host(Ct), ref, dt, A64, B64, what="pack paths C tn %s" % (case,))
+    rA, rB = oracle.backward(A64, B64, G64)
+    check(host(dA), rA, dt, G64, B64.T, what="pack paths dA %s" % (case,))
+    check(host(dB), rB, dt, A64.T, G64, what="pack paths dB %s" % (case,))
+
+
+@pytest.mark.parametrize("tn", [False, True])
+@pytest.mark.parametrize("p", [4, 3])
+def test_split3_pieces_reconstruct_exactly(tn, p):
+    """p = 4 and p = 3 (contraction blocks of 80 and 107: whole and ragged
+    chunks)."""
+    _skip_no_gpu()
+    m, k = 200, 320
     A, Af = to_dev(inputs.row_scaled((k, m) if tn else (m, k), seed=901), "split3_bf16")
     D64, d = _pow2_diag(k, 902)
     D, _ = to_dev(D64, "split3_bf16")
     note("split pieces, static side, tn=%s" % tn)
-    C = (hs.hs_gemm_tn if tn else hs.hs_gemm)(A, D, dtype="split3_bf16", p=p, K=2)
+    C = (hs.hs_gemm_tn if tn else hs.hs_gemm)(A, D, dtype="split3_bf16", p=p, K=2 if p % 2 == 0 else 1)
     Aop = Af.T if tn else Af                       # the operand as it multiplies
     assert np.array_equal(host(C), Aop * d[None, :])
     # travelling side: diag(d) . B
     B, Bf = to_dev(inputs.row_scaled((k, m), seed=903), "split3_bf16")
     note("split pieces, travelling side, tn=%s" % tn)
-    C2 = (hs.hs_gemm_tn if tn else hs.hs_gemm)(D, B, dtype="split3_bf16", p=p, K=2)
+    C2 = (hs.hs_gemm_tn if tn else hs.hs_gemm)(D, B, dtype="split3_bf16", p=p, K=2 if p % 2 == 0 else 1)
     assert np.array_equal(host(C2), d[:, None] * Bf)
 
 
-def test_split3_pieces_reconstruct_exactly_backward():
-    """dA = G . B^T (NT) with B diagonal, dB = A^T . G (TN) with A diagonal."""
+@pytest.mark.parametrize("p", [4, 3])
+def test_split3_pieces_reconstruct_exactly_backward(p):
+    """dA = G . B^T (NT) with B diagonal, dB = A^T . G (TN) with A diagonal;
+    p = 4 and p = 3 (whole and ragged chunks)."""
     _skip_no_gpu()
     n = 256
     G, Gf = to_dev(inputs.row_scaled((n, n), seed=904), "split3_bf16")
@@ -436,7 +492,7 @@ def test_split3_pieces_reconstruct_exactly_backward():
     DA, _ = to_dev(DA64, "split3_bf16")
     DB, _ = to_dev(DB64, "split3_bf16")
     note("split pieces, backward")
-    dA, dB = hs.hs_gemm_backward(DA, DB, G, dtype="split3_bf16", p=4, K=2)
+    dA, dB = hs.hs_gemm_backward(DA, DB, G, dtype="split3_bf16", p=p, K=1)
     assert np.array_equal(host(dA), Gf * db[None, :])
     assert np.array_equal(host(dB), da[:, None] * Gf)
 
