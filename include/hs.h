@@ -97,7 +97,11 @@ extern "C" {
  *                  hs_gemm_backward (dA = G B^H, dB = A^H G).
  *  HS_C32_SPLIT3_BF16  the same with the split-BF16 arithmetic of
  *                  HS_SPLIT3_BF16 (FP32-accurate).  hs_gemm, hs_gemm_tn and
- *                  hs_gemm_backward. */
+ *                  hs_gemm_backward.
+ *
+ * The entry points take the dtype (and hs_workspace_size its op) as a plain
+ * int, so that any value a caller passes is well defined: one that is not
+ * an hs_dtype gives HS_ERR_NOT_SUPPORTED (SIZE_MAX from hs_workspace_size). */
 typedef enum {
     HS_F64 = 0,
     HS_F32 = 1,
@@ -139,8 +143,10 @@ typedef struct {
     int32_t K;
 } hs_schedule;
 
-/* Human-readable name of a status code (static string, never NULL). */
-const char *hs_status_string(hs_status s);
+/* Human-readable name of a status code (static string, never NULL).  Takes
+ * any int, so that a caller may pass whatever it received: a value that is
+ * not an hs_status gives "unknown hs_status". */
+const char *hs_status_string(int status);
 
 /* Resolve K == 0 to its default and validate the schedule.
  * Host only.  Returns HS_ERR_INVALID_VALUE if p < 1, p > 4096, K < 0 or
@@ -158,8 +164,8 @@ hs_status hs_schedule_table(hs_schedule s, int32_t *out, size_t cap);
 /* Bytes of device workspace that `op` needs for these sizes (m, n, k as in
  * the corresponding call; for HS_OP_GEMV k is ignored).  Returns 0 if none
  * is needed, and SIZE_MAX if the arguments are invalid. */
-size_t hs_workspace_size(hs_op op, int64_t m, int64_t n, int64_t k,
-                         hs_dtype dtype, hs_schedule s);
+size_t hs_workspace_size(int op, int64_t m, int64_t n, int64_t k,
+                         int dtype, hs_schedule s);
 
 /* C[m, n] = A[m, k] . B[k, n]  (Eq. PRODUCT; Algorithm HYPER-SYSTOLIC).
  * A: m x k, lda >= k.  B: k x n, ldb >= n.  C: m x n, ldc >= n (written,
@@ -167,7 +173,7 @@ size_t hs_workspace_size(hs_op op, int64_t m, int64_t n, int64_t k,
  * count complex elements; pointers 8-byte aligned).  m, n or k may be 0
  * (k == 0 writes zeros).  hs_workspace_size(HS_OP_GEMM, m, n, k, ...) of a
  * complex dtype is that of the real product m x 2k times 2k x 2n. */
-hs_status hs_gemm(int64_t m, int64_t n, int64_t k, hs_dtype dtype, hs_schedule s,
+hs_status hs_gemm(int64_t m, int64_t n, int64_t k, int dtype, hs_schedule s,
                   const void *A, int64_t lda, const void *B, int64_t ldb,
                   void *C, int64_t ldc, void *ws, size_t ws_bytes, void *stream);
 
@@ -177,7 +183,7 @@ hs_status hs_gemm(int64_t m, int64_t n, int64_t k, hs_dtype dtype, hs_schedule s
  * All dtypes; for the complex ones C = A^T B (transposed, not conjugated),
  * sizes and ld* in complex elements, pointers 8-byte aligned, and the
  * workspace of the real product m x 2k times 2k x 2n. */
-hs_status hs_gemm_tn(int64_t m, int64_t n, int64_t k, hs_dtype dtype, hs_schedule s,
+hs_status hs_gemm_tn(int64_t m, int64_t n, int64_t k, int dtype, hs_schedule s,
                      const void *A, int64_t lda, const void *B, int64_t ldb,
                      void *C, int64_t ldc, void *ws, size_t ws_bytes, void *stream);
 
@@ -188,7 +194,7 @@ hs_status hs_gemm_tn(int64_t m, int64_t n, int64_t k, hs_dtype dtype, hs_schedul
  * (complex64 A, x, y; lda in complex elements; pointers 8-byte aligned; the
  * real and imaginary partial sums combined in FP64).  lda >= n.
  * Needs no workspace (ws may be NULL). */
-hs_status hs_gemv(int64_t m, int64_t n, hs_dtype dtype, hs_schedule s,
+hs_status hs_gemv(int64_t m, int64_t n, int dtype, hs_schedule s,
                   const void *A, int64_t lda, const void *x, void *y,
                   void *ws, size_t ws_bytes, void *stream);
 
@@ -202,7 +208,7 @@ hs_status hs_gemv(int64_t m, int64_t n, hs_dtype dtype, hs_schedule s,
  * hs_gemm (G has the input type).  For the complex dtypes the gradients are
  * dA = G . B^H and dB = A^H . G (conjugate transposes; G = dL/dC in the
  * convention where a real loss L has gradient dL/dre + i dL/dim). */
-hs_status hs_gemm_backward(int64_t m, int64_t n, int64_t k, hs_dtype dtype, hs_schedule s,
+hs_status hs_gemm_backward(int64_t m, int64_t n, int64_t k, int dtype, hs_schedule s,
                            const void *A, int64_t lda, const void *B, int64_t ldb,
                            const void *G, int64_t ldg,
                            void *dA, int64_t ldda, void *dB, int64_t lddb,
@@ -232,7 +238,7 @@ hs_status hs_gemm_backward(int64_t m, int64_t n, int64_t k, hs_dtype dtype, hs_s
  * position (their term is infinite).  n == 0 is a no-op; n < 2^31.
  * Workspace: hs_workspace_size(HS_OP_NBODY, n, 0, 0, dtype, s) bytes
  * (K n 4 values; none for K == 1). */
-hs_status hs_nbody(int64_t n, hs_dtype dtype, hs_schedule s, const void *bodies, double eps2, void *out,
+hs_status hs_nbody(int64_t n, int dtype, hs_schedule s, const void *bodies, double eps2, void *out,
                    void *ws, size_t ws_bytes, void *stream);
 
 /* Bytes of the static scratch array of hs_gemm_noalloc (per device). */
@@ -252,7 +258,7 @@ hs_status hs_nbody(int64_t n, hs_dtype dtype, hs_schedule s, const void *bodies,
  * runtime cannot give the scratch array's device address.  All calls on one
  * device share its scratch array: calls that overlap in time on one device
  * race and must be ordered by the caller (one stream, or events). */
-hs_status hs_gemm_noalloc(int64_t m, int64_t n, int64_t k, hs_dtype dtype, hs_schedule s,
+hs_status hs_gemm_noalloc(int64_t m, int64_t n, int64_t k, int dtype, hs_schedule s,
                           const void *A, int64_t lda, const void *B, int64_t ldb,
                           void *C, int64_t ldc, void *stream);
 

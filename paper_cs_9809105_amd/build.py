@@ -4,6 +4,10 @@
 
 Compiles in-tree with hipcc; the result sits next to this file so that it
 travels with the source tree.  Every build recompiles.
+
+``build(out=..., extra=...)`` writes a variant elsewhere with extra flags
+(the sanitized copy of the CPU test-suite); the product library is always
+``libhs.so`` beside this file.
 """
 import os
 import subprocess
@@ -26,20 +30,21 @@ FLAGS = [
 ]
 
 
-def build(verbose=False, extra=()):
-    tmp = LIB + ".tmp"
+def build(verbose=False, extra=(), out=None):
+    target = out or LIB
+    tmp = target + ".tmp"
     cmd = [HIPCC] + FLAGS + list(extra) + SOURCES + ["-o", tmp]
     if verbose:
         cmd.insert(1, "-Rpass-analysis=kernel-resource-usage")
     res = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
-    out = "\n".join(l for l in res.stdout.splitlines()
+    log = "\n".join(l for l in res.stdout.splitlines()
                     if "packed-fp32-ops' is not a recognized feature" not in l)
     if res.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + out)
-    os.replace(tmp, LIB)
-    if verbose and out.strip():
-        print(out)
-    return LIB
+        raise RuntimeError("hipcc failed:\n" + log)
+    os.replace(tmp, target)
+    if verbose and log.strip():
+        print(log)
+    return target
 
 
 if __name__ == "__main__":

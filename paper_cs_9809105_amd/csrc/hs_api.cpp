@@ -44,7 +44,7 @@ struct FormInfo {
     int fam, form, pack, in_esz, out_f64, packed_esz;
 };
 
-bool form_info(hs_dtype dt, FormInfo *f) {
+bool form_info(int dt, FormInfo *f) {
     switch (dt) {
         case HS_F64: *f = {FAM_F64, 0, PK_F64, 8, 1, 8}; return true;
         case HS_F32: *f = {FAM_F32, 0, PK_F32, 4, 0, 4}; return true;
@@ -58,7 +58,7 @@ bool form_info(hs_dtype dt, FormInfo *f) {
 }
 
 // The complex dtypes run as one real product of their base form.
-bool complex_base(hs_dtype dt, hs_dtype *base) {
+bool complex_base(int dt, hs_dtype *base) {
     if (dt == HS_C32) { *base = HS_F32; return true; }
     if (dt == HS_C32_SPLIT3_BF16) { *base = HS_SPLIT3_BF16; return true; }
     return false;
@@ -94,7 +94,7 @@ int64_t pack_units(const OperandGeom &g, int kmajor) {
 }
 
 // Geometry of one product C[M,N] = X[M,Kd] Y[Kd,N] under schedule (p, K).
-hs_status make_plan(int64_t M, int64_t N, int64_t Kd, hs_dtype dt, hs_schedule s, Plan *P) {
+hs_status make_plan(int64_t M, int64_t N, int64_t Kd, int dt, hs_schedule s, Plan *P) {
     if (!form_info(dt, &P->f)) return HS_ERR_NOT_SUPPORTED;
     hs_schedule r;
     hs_status st = hs_schedule_resolve(s, &r);
@@ -324,7 +324,7 @@ hs_status check_ws(const Plan &P, const void *ws, size_t ws_bytes) {
 // (56 VGPRs, 8 waves per SIMD) measured fastest at n = 2^18, K = 8:
 // 3.48 T pairs/s against 3.34 (4) and 3.17 (8).
 const int kNbodyKR = 2;
-hs_status nbody_plan(int64_t n, hs_dtype dtype, hs_schedule s, double eps2, NbodyArgs *a, int *kr,
+hs_status nbody_plan(int64_t n, int dtype, hs_schedule s, double eps2, NbodyArgs *a, int *kr,
                      size_t *ws) {
     if (dtype != HS_F32 && dtype != HS_F64) return HS_ERR_NOT_SUPPORTED;
     hs_schedule r;
@@ -353,8 +353,8 @@ hs_status nbody_plan(int64_t n, hs_dtype dtype, hs_schedule s, double eps2, Nbod
 
 extern "C" {
 
-const char *hs_status_string(hs_status s) {
-    switch (s) {
+const char *hs_status_string(int status) {
+    switch (status) {
         case HS_OK: return "HS_OK";
         case HS_ERR_INVALID_VALUE: return "HS_ERR_INVALID_VALUE: invalid argument";
         case HS_ERR_NOT_SUPPORTED: return "HS_ERR_NOT_SUPPORTED: dtype or size not supported for this call";
@@ -391,7 +391,7 @@ hs_status hs_schedule_table(hs_schedule s, int32_t *out, size_t cap) {
     return HS_OK;
 }
 
-size_t hs_workspace_size(hs_op op, int64_t m, int64_t n, int64_t k, hs_dtype dtype, hs_schedule s) {
+size_t hs_workspace_size(int op, int64_t m, int64_t n, int64_t k, int dtype, hs_schedule s) {
     const size_t bad = std::numeric_limits<size_t>::max();
     Plan P;
     switch (op) {
@@ -443,7 +443,7 @@ size_t hs_workspace_size(hs_op op, int64_t m, int64_t n, int64_t k, hs_dtype dty
     return bad;
 }
 
-hs_status hs_gemm(int64_t m, int64_t n, int64_t k, hs_dtype dtype, hs_schedule s,
+hs_status hs_gemm(int64_t m, int64_t n, int64_t k, int dtype, hs_schedule s,
                   const void *A, int64_t lda, const void *B, int64_t ldb,
                   void *C, int64_t ldc, void *ws, size_t ws_bytes, void *stream) {
     hs_dtype base;
@@ -468,7 +468,7 @@ hs_status hs_gemm(int64_t m, int64_t n, int64_t k, hs_dtype dtype, hs_schedule s
     return run_product(P, Operand{A, lda, 1, EMB_NONE}, Operand{B, ldb, 0, EMB_NONE}, C, ldc, ws, (hipStream_t)stream);
 }
 
-hs_status hs_gemm_tn(int64_t m, int64_t n, int64_t k, hs_dtype dtype, hs_schedule s,
+hs_status hs_gemm_tn(int64_t m, int64_t n, int64_t k, int dtype, hs_schedule s,
                      const void *A, int64_t lda, const void *B, int64_t ldb,
                      void *C, int64_t ldc, void *ws, size_t ws_bytes, void *stream) {
     hs_dtype base;
@@ -493,7 +493,7 @@ hs_status hs_gemm_tn(int64_t m, int64_t n, int64_t k, hs_dtype dtype, hs_schedul
     return run_product(P, Operand{A, lda, 0, EMB_NONE}, Operand{B, ldb, 0, EMB_NONE}, C, ldc, ws, (hipStream_t)stream);
 }
 
-hs_status hs_gemv(int64_t m, int64_t n, hs_dtype dtype, hs_schedule s,
+hs_status hs_gemv(int64_t m, int64_t n, int dtype, hs_schedule s,
                   const void *A, int64_t lda, const void *x, void *y,
                   void *ws, size_t ws_bytes, void *stream) {
     (void)ws;
@@ -534,7 +534,7 @@ hs_status hs_gemv(int64_t m, int64_t n, hs_dtype dtype, hs_schedule s,
     return launch_status(e);
 }
 
-hs_status hs_gemm_backward(int64_t m, int64_t n, int64_t k, hs_dtype dtype, hs_schedule s,
+hs_status hs_gemm_backward(int64_t m, int64_t n, int64_t k, int dtype, hs_schedule s,
                            const void *A, int64_t lda, const void *B, int64_t ldb,
                            const void *G, int64_t ldg,
                            void *dA, int64_t ldda, void *dB, int64_t lddb,
@@ -587,7 +587,7 @@ hs_status hs_gemm_backward(int64_t m, int64_t n, int64_t k, hs_dtype dtype, hs_s
     return HS_OK;
 }
 
-hs_status hs_nbody(int64_t n, hs_dtype dtype, hs_schedule s, const void *bodies, double eps2, void *out,
+hs_status hs_nbody(int64_t n, int dtype, hs_schedule s, const void *bodies, double eps2, void *out,
                    void *ws, size_t ws_bytes, void *stream) {
     NbodyArgs a;
     int kr;

@@ -42,7 +42,7 @@ void *scratch_on_current_device() {
 
 }  // namespace
 
-extern "C" hs_status hs_gemm_noalloc(int64_t m, int64_t n, int64_t k, hs_dtype dtype, hs_schedule s,
+extern "C" hs_status hs_gemm_noalloc(int64_t m, int64_t n, int64_t k, int dtype, hs_schedule s,
                                      const void *A, int64_t lda, const void *B, int64_t ldb,
                                      void *C, int64_t ldc, void *stream) {
     // hs_gemm's own argument checks first: with no workspace it returns

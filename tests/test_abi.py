@@ -45,6 +45,7 @@ def test_status_strings():
     for s in range(6):
         assert B.hs_status_string(s).startswith("HS_")
     assert B.hs_status_string(99) == "unknown hs_status"
+    assert B.hs_status_string(-1) == "unknown hs_status"
 
 
 @pytest.mark.parametrize("p", [1, 2, 4, 6, 9, 12, 16, 36, 64, 100])
@@ -131,6 +132,10 @@ def test_workspace_sizes():
     assert ws(B.HS_OP_GEMV, 100, 100, 0, "bf16", 4) == B.SIZE_MAX
     assert ws(B.HS_OP_GEMM, 10, 10, 10, "f32", 3, 2) == B.SIZE_MAX
     assert ws(B.HS_OP_GEMM, 10, 10, 10, 99, 2) == B.SIZE_MAX
+    # dtype and op are plain ints in the ABI: any value is a defined input
+    assert ws(B.HS_OP_GEMM, 10, 10, 10, -1, 2) == B.SIZE_MAX
+    assert ws(99, 10, 10, 10, "f32", 2) == B.SIZE_MAX
+    assert ws(-7, 10, 10, 10, "f32", 2) == B.SIZE_MAX
     s1 = ws(B.HS_OP_GEMM, 1024, 1024, 1024, "f32", 8, 1)
     s2 = ws(B.HS_OP_GEMM, 1024, 1024, 1024, "f32", 8, 2)
     s8 = ws(B.HS_OP_GEMM, 1024, 1024, 1024, "f32", 8, 8)

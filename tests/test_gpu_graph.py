@@ -70,19 +70,18 @@ def test_graph_replays_match_eager():
         assert torch.equal(F, F_ref), r
 
 
-def test_graph_of_many_phases_and_complex():
-    """A product whose partial planes run in several column phases (each
-    phase a main launch and a back-shift) and a complex product, captured
-    together."""
+def test_graph_of_k8_product_and_complex():
+    """A K = 8 product (every output tile collects eight partials) at a
+    size with many workgroups, and a complex product, captured together."""
     _skip_no_gpu()
-    m, k, n = 4096, 512, 4096                   # K = 8: 8 planes of 4096 x 256 per tile
+    m, k, n = 4096, 512, 4096                   # p = 64, K = 8: 64-row stripes, 4 per tile
     A = torch.from_numpy(inputs.normal((m, k), 61)).float().cuda()
     B = torch.from_numpy(inputs.normal((k, n), 62)).float().cuda()
     Z = torch.from_numpy((inputs.normal((300, 200), 63) + 1j * inputs.normal((300, 200), 64))
                          .astype(np.complex64)).cuda()
     W = torch.from_numpy((inputs.normal((200, 100), 65) + 1j * inputs.normal((200, 100), 66))
                          .astype(np.complex64)).cuda()
-    note("graph phases: eager reference")
+    note("graph k8: eager reference")
     C_ref = hs.hs_gemm(A, B, dtype="f32", p=64, K=8)
     Y_ref = hs.hs_gemm(Z, W, dtype="c32_split3_bf16", p=4, K=2)
     torch.cuda.synchronize()
@@ -95,7 +94,7 @@ def test_graph_of_many_phases_and_complex():
         hs.hs_gemm(Z, W, dtype="c32_split3_bf16", p=4, K=2, out=Y)
     torch.cuda.current_stream().wait_stream(s)
     torch.cuda.synchronize()
-    note("graph phases: capture")
+    note("graph k8: capture")
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g):
         hs.hs_gemm(A, B, dtype="f32", p=64, K=8, out=C)
@@ -104,7 +103,7 @@ def test_graph_of_many_phases_and_complex():
         C.fill_(float("nan"))
         Y.fill_(complex(float("nan"), 0.0))
         torch.cuda.synchronize()
-        note("graph phases: replay", r)
+        note("graph k8: replay", r)
         g.replay()
         torch.cuda.synchronize()
         assert torch.equal(C, C_ref), r
