@@ -17,6 +17,13 @@ shared with the HIP path:
   a tile of zeros), q0 = e4m3(a 2^e), and for the refined form e1 = the same
   exponent for the residuals a 2^e - q0, q1 = e4m3((a 2^e - q0) 2^e1).
   Dequantised: q0 2^-e, refined q0 2^-e + q1 2^-(e + e1).
+* f16(x): IEEE binary16, round to nearest, ties to even: 11 significant
+  bits, smallest normal 2^-14, subnormal spacing 2^-24, largest finite 65504.
+* 2-piece FP16 split with a power-of-two scale per operand row (row = the
+  non-contraction index): e = the largest integer with amax * 2^e < 2^15
+  (15 for a row of zeros), x' = x 2^e, a0 = f16(x'), a1 = f16(x' - a0).
+  The element stands for (a0 + a1) 2^-e; a product keeps a0 b0 + a0 b1 +
+  a1 b0 and scales the sum by 2^-(e_row + e_col).
 
 Pins: tests/test_oracle_precision.py (torch's own bfloat16 and float8_e4m3fn
 conversions, the table's structure, tie cases, error bounds).
@@ -119,3 +126,57 @@ def split3(a):
     a1 = bf16(r1)
     a2 = bf16(r1 - a1)
     return a0, a1, a2
+
+
+def f16(x):
+    """Round to IEEE binary16 (11 significant bits), ties to even, as float64.
+
+    From the definition, as bf16 above: the leading bit of |x| scaled to 2^10,
+    rounded to an integer with ties to even, scaled back; exponents below -14
+    share the subnormal spacing 2^-24; results past the largest finite value
+    65504 (from 65520 on, the rounding boundary) become infinite."""
+    x = np.asarray(x, np.float64)
+    ax = np.abs(x)
+    with np.errstate(divide="ignore"):
+        E = np.where(ax > 0, np.floor(np.log2(np.where(ax > 0, ax, 1.0))), 0.0)
+    E = np.where(ax >= 2.0 ** (E + 1), E + 1, E)
+    E = np.where(ax < 2.0 ** E, E - 1, E)
+    E = np.maximum(E, -14.0)
+    q = np.rint(ax * 2.0 ** (10 - E)) * 2.0 ** (E - 10)
+    q = np.where(q >= 65520.0, np.inf, q)
+    return np.sign(x) * q
+
+
+def row_exponent(amax):
+    """Largest integer e with amax * 2^e < 2^15; 15 when amax == 0."""
+    amax = float(amax)
+    if amax == 0.0:
+        return 15
+    e = int(np.floor(15 - np.log2(amax)))
+    while amax * 2.0 ** e >= 2.0 ** 15:            # settle log2 rounding
+        e -= 1
+    while amax * 2.0 ** (e + 1) < 2.0 ** 15:
+        e += 1
+    return e
+
+
+def split2_f16(X, row_axis=0):
+    """Pieces of the 2-piece FP16 split: (a0, a1, e) with a0, a1 in the
+    scaled domain (float64 arrays shaped like X) and e the exponent of each
+    row (rows along ``row_axis``, the contraction along the other axis)."""
+    X = np.asarray(X, np.float32).astype(np.float64)
+    Xr = X if row_axis == 0 else X.T
+    e = np.array([row_exponent(np.max(np.abs(r)) if r.size else 0.0) for r in Xr], dtype=np.int64)
+    xs = Xr * np.ldexp(1.0, e)[:, None]            # exact: a power of two
+    a0 = f16(xs)
+    a1 = f16(xs - a0)                              # the residual is exact in float64
+    if row_axis != 0:
+        a0, a1 = a0.T, a1.T
+    return a0, a1, e
+
+
+def split2_f16_value(X, row_axis=0):
+    """The value each element of X stands for in the 2-piece FP16 form."""
+    a0, a1, e = split2_f16(X, row_axis)
+    scale = np.ldexp(1.0, -e)
+    return (a0 + a1) * (scale[:, None] if row_axis == 0 else scale[None, :])

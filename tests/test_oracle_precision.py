@@ -89,3 +89,69 @@ def test_split3_reconstructs_exactly_in_normal_range():
     assert np.array_equal(a0 + a1 + a2, a.astype(np.float64))
     nz = a1 != 0
     assert np.all(np.abs(a1[nz]) <= np.abs(a0[nz]) * 2.0 ** -8)
+
+
+def test_f16_matches_numpy_and_torch_float16():
+    rng = np.random.default_rng(16)
+    y = (rng.standard_normal(100000) * 2.0 ** rng.uniform(-30, 17, 100000)).astype(np.float32)
+    # exact ties of 11 significant bits, normal and subnormal
+    ties = ((rng.integers(1024, 2048, 2000) * 2 + 1) * 2.0 ** rng.integers(-25, 5, 2000))
+    sub = (rng.integers(0, 2048, 2000) * 2 + 1) * 2.0 ** -25
+    for x in (y.astype(np.float64), ties, -ties, sub):
+        with np.errstate(over="ignore"):            # past 65520: infinity on both sides
+            ref = x.astype(np.float16).astype(np.float64)
+        assert np.array_equal(P.f16(x), ref)
+        assert np.array_equal(P.f16(x), torch.from_numpy(x).to(torch.float16).double().numpy())
+    assert P.f16(65519.0) == 65504.0 and P.f16(65520.0) == np.inf and P.f16(2.0 ** -25) == 0.0
+    assert P.f16(3 * 2.0 ** -26) == 2.0 ** -24
+
+
+def test_row_exponent_definition():
+    rng = np.random.default_rng(17)
+    for amax in np.concatenate([2.0 ** rng.uniform(-140, 120, 2000), [1.0, 2.0 ** 15, 3.0, 2.0 ** -149]]):
+        e = P.row_exponent(amax)
+        assert 2.0 ** 14 <= amax * 2.0 ** e < 2.0 ** 15, amax
+    assert P.row_exponent(0.0) == 15
+    assert P.row_exponent(1.0) == 14 and P.row_exponent(1.5) == 14 and P.row_exponent(0.5) == 15
+
+
+def test_split2_f16_hand_value():
+    # float32(1/3) = 11184811 * 2^-25, row max 1/3: e = 16 (2^16/3 lies in
+    # [2^14, 2^15)), x' = 11184811 / 512 = 21845.333984375; binary16 spacing
+    # at 2^14 is 16: a0 = 21840; the residual 2731/512 = 5.333984375 has
+    # spacing 2^-8 and sits exactly halfway between 1365 and 1366 units: the
+    # tie goes to the even one, a1 = 1366/256
+    a0, a1, e = P.split2_f16(np.array([[np.float32(1.0 / 3.0)]]))
+    assert e.tolist() == [16]
+    assert a0[0, 0] == 21840.0 and a1[0, 0] == 1366.0 / 256.0
+    v = P.split2_f16_value(np.array([[np.float32(1.0 / 3.0)]]))
+    assert v[0, 0] == (21840.0 + 1366.0 / 256.0) * 2.0 ** -16
+
+
+def test_split2_f16_error_bound_and_structure():
+    rng = np.random.default_rng(18)
+    X = (rng.standard_normal((64, 300)) * 10.0 ** rng.uniform(-30, 30, (64, 1))).astype(np.float32)
+    X[3, :] = 0.0
+    X[5, 7] = 0.0
+    for axis in (0, 1):
+        Y = X if axis == 0 else X.T
+        a0, a1, e = P.split2_f16(Y, row_axis=axis)
+        xs = X * np.ldexp(1.0, e)[:, None]
+        A0 = a0 if axis == 0 else a0.T
+        A1 = a1 if axis == 0 else a1.T
+        for q in (A0, A1):                          # each piece is a binary16 value
+            assert np.array_equal(P.f16(q), q)
+        amax = np.max(np.abs(xs), axis=1)
+        nz = amax > 0
+        assert np.all((amax[nz] >= 2.0 ** 14) & (amax[nz] < 2.0 ** 15))
+        # |x' - a0 - a1| <= 2^-22 |x'| + 2^-25 (the last term: subnormal a1)
+        err = np.abs(xs - A0 - A1)
+        assert np.all(err <= 2.0 ** -22 * np.abs(xs) + 2.0 ** -25)
+        assert np.all(np.abs(xs - A0) <= 2.0 ** -11 * np.abs(xs) + 2.0 ** -25)
+        val = P.split2_f16_value(Y, row_axis=axis)
+        V = val if axis == 0 else val.T
+        assert np.all(np.abs(V - X) <= (2.0 ** -22 * np.abs(xs) + 2.0 ** -25) * np.ldexp(1.0, -e)[:, None])
+    # small integers and powers of two are exact
+    Z = rng.integers(-8, 9, (32, 40)).astype(np.float32) * np.float32(2.0 ** -3)
+    assert np.array_equal(P.split2_f16_value(Z), Z.astype(np.float64))
+    assert np.array_equal(P.split2_f16_value(Z, row_axis=1), Z.astype(np.float64))
