@@ -33,9 +33,10 @@ VALU_F32_PEAK = PEAK["f32"]
 # distance plus softening, 1 reciprocal square root, 4 products / differences
 # for the potential and the factor m / s^(3/2), 3 FMAs into the acceleration
 NBODY_FLOPS = 20
-MFMA_PRODUCTS = {"split3_bf16": 6, "bf16": 1, "f16": 1, "f32": 1, "f64": 1, "fp8_e4m3": 1, "fp8_e4m3_r1": 3}
+MFMA_PRODUCTS = {"split3_bf16": 6, "bf16": 1, "f16": 1, "f32": 1, "f64": 1, "fp8_e4m3": 1, "fp8_e4m3_r1": 3,
+                 "split2_f16": 3}
 MFMA_PEAK_KEY = {"split3_bf16": "bf16", "bf16": "bf16", "f16": "f16", "f32": "f32", "f64": "f64",
-                 "fp8_e4m3": "fp8", "fp8_e4m3_r1": "fp8"}
+                 "fp8_e4m3": "fp8", "fp8_e4m3_r1": "fp8", "split2_f16": "f16"}
 
 
 def parse():
@@ -51,7 +52,8 @@ def parse():
     ap.add_argument("--p", type=int, default=64)
     ap.add_argument("--K", type=int, default=None, help="K of the schedule (2; 8 for nbody)")
     ap.add_argument("--form", default="split3_bf16")
-    ap.add_argument("--compare", default="f32", help="form timed beside the headline ('' to skip)")
+    ap.add_argument("--compare", default="f32,split2_f16",
+                    help="comma-separated forms timed beside the headline ('' to skip)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle baseline sample (0 to skip)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -475,22 +477,25 @@ def main():
     achieved = mfma_flops / (kern_ms * 1e-3) / 1e12
     peak = PEAK[MFMA_PEAK_KEY[args.form]]
 
-    # the timed step's outputs, kept on the GPU for the accuracy check
-    outs_cmp = None
+    # the timed steps' outputs, kept on the GPU for the accuracy check
+    outs_cmp = {}
     comparison = None
-    if args.compare:
+    for cf in [c for c in args.compare.split(",") if c]:
         s2 = max(2, args.steps // 2)
-        w2, k2, l2, outs_cmp = run_form(hs, torch, A, B, G, args.compare, p, K, s2, 1)
-        comparison = {args.compare: {"value": useful * s2 / w2 / 1e12, "ms_per_step": w2 * 1e3 / s2,
-                                     "avg_main_kernel_ms": k2 / max(l2, 1)}}
+        w2, k2, l2, outs_cmp[cf] = run_form(hs, torch, A, B, G, cf, p, K, s2, 1)
+        f2 = MFMA_PRODUCTS[cf] * 2.0 * m * kd * n * 3 * s2 / (k2 * 1e-3) / 1e12
+        comparison = comparison or {}
+        comparison[cf] = {"value": useful * s2 / w2 / 1e12, "ms_per_step": w2 * 1e3 / s2,
+                          "avg_main_kernel_ms": k2 / max(l2, 1),
+                          "mfma_frac": f2 / PEAK[MFMA_PEAK_KEY[cf]]}
 
     cpu = None
     acc = None
     if args.cpu_seconds > 0:
         cpu, ref = cpu_baseline(A64, B64, G64, args.cpu_seconds)
         acc = {args.form: accuracy(outs, ref)}
-        if outs_cmp is not None:
-            acc[args.compare] = accuracy(outs_cmp, ref)
+        for cf, o in outs_cmp.items():
+            acc[cf] = accuracy(o, ref)
 
     square = m == kd == n
     shape_txt = "square n=%d" % n if square else "A %dx%d, B %dx%d" % (m, kd, kd, n)

@@ -98,6 +98,15 @@ extern "C" {
  *  HS_C32_SPLIT3_BF16  the same with the split-BF16 arithmetic of
  *                  HS_SPLIT3_BF16 (FP32-accurate).  hs_gemm, hs_gemm_tn and
  *                  hs_gemm_backward.
+ *  HS_SPLIT2_F16   in f32,  out f32.  Each operand row r (its non-contraction
+ *                  index) is scaled by 2^e_r, e_r the largest integer with
+ *                  max|row| 2^e_r < 2^15, and split as a' = a0 + a1 with f16
+ *                  pieces a0 = f16(a'), a1 = f16(a' - a0) (round to nearest
+ *                  even; 22 significant bits); the three products a0 b0,
+ *                  a0 b1, a1 b0 on FP16 MFMA into one FP32 accumulator, the
+ *                  result scaled back by 2^-(e_row + e_col).  FP32-level
+ *                  accuracy with half the MFMA work of HS_SPLIT3_BF16.
+ *                  hs_gemm, hs_gemm_tn and hs_gemm_backward.
  *
  * The entry points take the dtype (and hs_workspace_size its op) as a plain
  * int, so that any value a caller passes is well defined: one that is not
@@ -111,7 +120,8 @@ typedef enum {
     HS_FP8_E4M3 = 5,
     HS_FP8_E4M3_R1 = 6,
     HS_C32 = 7,
-    HS_C32_SPLIT3_BF16 = 8
+    HS_C32_SPLIT3_BF16 = 8,
+    HS_SPLIT2_F16 = 9
 } hs_dtype;
 
 typedef enum {

@@ -24,6 +24,7 @@ hipError_t launch_backshift(int f64, const void *W, int64_t plane, int K, int64_
 hipError_t launch_fill_zero(int f64, void *Cout, int64_t M, int64_t N, int64_t ldc, hipStream_t st);
 hipError_t launch_gemv(int f64, const GemvArgs &a, hipStream_t st);
 hipError_t launch_fp8_exps(const Fp8ExpArgs &a, int64_t tiles, hipStream_t st);
+hipError_t launch_row_amax(const RowAmaxArgs &a, hipStream_t st);
 hipError_t launch_nbody(int f64, const void *bodies, void *out, const NbodyArgs &a, int kr, hipStream_t st);
 int mm_tile_rows(int fam);
 int mm_tile_cols(int fam);
@@ -53,6 +54,7 @@ bool form_info(int dt, FormInfo *f) {
         case HS_SPLIT3_BF16: *f = {FAM_BF16, 1, PK_SPLIT3, 4, 0, 2}; return true;
         case HS_FP8_E4M3: *f = {FAM_FP8, 0, PK_FP8, 4, 0, 1}; return true;
         case HS_FP8_E4M3_R1: *f = {FAM_FP8, 1, PK_FP8, 4, 0, 1}; return true;
+        case HS_SPLIT2_F16: *f = {FAM_F16, 2, PK_SPLIT2F16, 4, 0, 2}; return true;
         default: return false;
     }
 }
@@ -119,7 +121,8 @@ hs_status make_plan(int64_t M, int64_t N, int64_t Kd, int dt, hs_schedule s, Pla
     // residue class mod K (they share every travelling block)
     const int MS = (int)std::min<int64_t>(BMT, S_r);
     P->G = (int)std::max<int64_t>(1, std::min<int64_t>(P->Kt, BMT / MS));
-    const int NP = fp8 ? (P->f.form == 1 ? 2 : 1) : (P->f.form == 1 ? 3 : 1);
+    const int NP = fp8 ? (P->f.form == 1 ? 2 : 1) : (P->f.form == 1 ? 3 : P->f.form == 2 ? 2 : 1);
+    const bool rowscale = P->f.pack == PK_SPLIT2F16;
     if (fp8) {
         // every 32-row / 32-column MFMA tile and every 64-deep chunk must lie
         // inside one 128 x 128 scale tile: whole 64-chunks per block, 32-row
@@ -158,7 +161,8 @@ hs_status make_plan(int64_t M, int64_t N, int64_t Kd, int dt, hs_schedule s, Pla
     if ((int64_t)p * nch >= (int64_t)1 << 31) return HS_ERR_NOT_SUPPORTED;
 
     // workspace: the two packed operands (no partial planes: the collector
-    // keeps every partial in registers) and the FP8 tile exponents
+    // keeps every partial in registers), the FP8 tile exponents or the
+    // two-piece FP16 row amaxes
     size_t off = 0;
     P->off_a = off; off = align_up(off + (size_t)(a.n_groups * a.group_bytes));
     P->off_b = off; off = align_up(off + (size_t)(b.n_groups * b.group_bytes));
@@ -169,6 +173,10 @@ hs_status make_plan(int64_t M, int64_t N, int64_t Kd, int dt, hs_schedule s, Pla
     if (fp8) {
         P->off_ea = off; off = align_up(off + (size_t)P->tiles_ra * P->tiles_k * 2 * sizeof(int32_t));
         P->off_eb = off; off = align_up(off + (size_t)P->tiles_rb * P->tiles_k * 2 * sizeof(int32_t));
+    }
+    if (rowscale) {
+        P->off_ea = off; off = align_up(off + (size_t)M * sizeof(uint32_t));
+        P->off_eb = off; off = align_up(off + (size_t)N * sizeof(uint32_t));
     }
     P->total = (M == 0 || N == 0 || Kd == 0) ? 0 : off;
     return HS_OK;
@@ -198,7 +206,7 @@ int pack_vec_ok(const Plan &P, const Operand &X) {
     if (!X.kmajor || X.embed != EMB_NONE) return 0;
     const int64_t ue = 16 / P.f.packed_esz;          // source elements per unit
     const int64_t in = P.f.in_esz;
-    if (P.f.pack == PK_SPLIT3) {                     // 8 fp32 per unit (two loads)
+    if (P.f.pack == PK_SPLIT3 || P.f.pack == PK_SPLIT2F16) {   // 8 fp32 per unit (two loads)
         return (X.ld % 4 == 0 && aligned(X.ptr, 16) && P.ga.S_k % 8 == 0 && P.Kd % 8 == 0) ? 1 : 0;
     }
     if (P.f.pack == PK_FP8) {                        // 16 fp32 per unit (four loads)
@@ -212,7 +220,8 @@ int pack_vec_ok(const Plan &P, const Operand &X) {
 // 4-row run of a group lies in one stripe.
 bool pack_mn_ok(const Plan &P, const Operand &X, const OperandGeom &g) {
     if (X.kmajor || X.embed != EMB_NONE) return false;
-    if (P.f.pack != PK_F32 && P.f.pack != PK_SPLIT3 && P.f.pack != PK_FP8) return false;
+    if (P.f.pack != PK_F32 && P.f.pack != PK_SPLIT3 && P.f.pack != PK_FP8 && P.f.pack != PK_SPLIT2F16)
+        return false;
     return X.ld % 4 == 0 && aligned(X.ptr, 16) && g.grp_rows % 4 == 0 && (!g.striped || g.S_r % 4 == 0);
 }
 
@@ -236,6 +245,12 @@ hs_status run_product(const Plan &P, const Operand &X, const Operand &Y, void *o
         Fp8ExpArgs xb{(const float *)Y.ptr, Y.ld, Y.kmajor, P.N, P.Kd, P.tiles_k, P.f.form, eb};
         if (launch_fp8_exps(xa, P.tiles_ra * P.tiles_k, stream) != hipSuccess ||
             launch_fp8_exps(xb, P.tiles_rb * P.tiles_k, stream) != hipSuccess)
+            return HS_ERR_LAUNCH_FAILED;
+    }
+    if (P.f.pack == PK_SPLIT2F16) {   // row amaxes of both operands (their scales)
+        RowAmaxArgs xa{(const float *)X.ptr, X.ld, X.kmajor, P.M, P.Kd, (uint32_t *)ea};
+        RowAmaxArgs xb{(const float *)Y.ptr, Y.ld, Y.kmajor, P.N, P.Kd, (uint32_t *)eb};
+        if (launch_row_amax(xa, stream) != hipSuccess || launch_row_amax(xb, stream) != hipSuccess)
             return HS_ERR_LAUNCH_FAILED;
     }
 

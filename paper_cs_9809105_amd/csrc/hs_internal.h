@@ -30,6 +30,19 @@ enum PackKind : int {
     PK_B16 = 2,      // 16-bit -> same 16-bit (bf16 or f16 copy)
     PK_SPLIT3 = 3,   // f32 -> three bf16 pieces
     PK_FP8 = 4,      // f32 -> e4m3 q0 (+ q1) with per-tile power-of-two scales
+    PK_SPLIT2F16 = 5 // f32 -> two f16 pieces of x 2^e, e per operand row
+};
+
+// Two-piece FP16 split: each operand row (non-contraction index) r gets the
+// scale 2^e_r, e_r = the largest integer with amax_r 2^e_r < 2^15, found
+// from the row's amax (kept as its float bits, which order like unsigned
+// integers for amax >= 0): e_r = 15 - frexp_exp(amax_r) (15 for amax 0).
+struct RowAmaxArgs {
+    const float *src;
+    int64_t ld;
+    int kmajor;               // 1: row r is contiguous along the contraction
+    int64_t R, Kd;
+    uint32_t *amax;           // [R] float bits of max |x| over the row
 };
 
 // FP8 scale tiles: 128 x 128 blocks of the logical operand (rows x
@@ -71,7 +84,8 @@ struct PackArgs {
     void *dst;
     int64_t total_units;     // < 2^31
     int vec;                 // K-major source: 16-byte vector loads are legal
-    const int32_t *exps;     // fp8 only: tile exponents (Fp8ExpArgs)
+    const int32_t *exps;     // fp8: tile exponents (Fp8ExpArgs); two-piece FP16:
+                             // the rows' amax bits (RowAmaxArgs), as uint32
     int64_t exp_tiles_k;
     int refine;              // fp8 only: write q1 as the second piece
     int embed;               // complex sources (interleaved re, im; ld in
@@ -106,8 +120,8 @@ struct MainArgs {
     int64_t b_piece;
     int64_t b_group;
     int64_t a_span;          // bytes one workgroup addresses from its first group, < 4 GiB
-    const int32_t *a_exps;   // fp8 only: tile exponents of each operand
-    const int32_t *b_exps;
+    const int32_t *a_exps;   // fp8: tile exponents of each operand; two-piece
+    const int32_t *b_exps;   // FP16: each operand's row amax bits (uint32)
     int64_t a_tiles_k, b_tiles_k;
     int64_t S_k;             // contraction block length (fp8 scale lookup)
     int64_t Kd;              // contraction length

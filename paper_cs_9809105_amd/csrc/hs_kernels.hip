@@ -39,6 +39,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));   // 16 bytes, a native vector
@@ -174,12 +175,33 @@ __global__ __launch_bounds__(512) void fp8_tile_exp_kernel(Fp8ExpArgs a) {
     }
 }
 
+// Scale exponent of an operand row from its amax bits: the largest e with
+// amax 2^e < 2^15 is 15 - frexp_exp(amax) (frexp_exp(0) = 0: any e suits
+// a row of zeros).
+DEVI int row_scale_exp(uint32_t amax_bits) { return 15 - __builtin_amdgcn_frexp_expf(__uint_as_float(amax_bits)); }
+
+// Eight floats of one row -> the 16-byte units of their two FP16 pieces,
+// x' = x 2^e, a0 = f16(x'), a1 = f16(x' - a0): round to nearest even, the
+// residual exact in FP32 (a0 is within a factor 2 of x', or both lie below
+// 2^-14 on the 2^-24 grid).  Word j holds elements 2j (low half), 2j + 1.
+DEVI void split2_f16_units(const float (&x)[8], int e, u32x4 &p0, u32x4 &p1) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const f32x2 v = {ldexpf(x[2 * j], e), ldexpf(x[2 * j + 1], e)};   // exact
+        const f16x2 h0 = __builtin_convertvector(v, f16x2);
+        const f32x2 r = v - __builtin_convertvector(h0, f32x2);
+        p0[j] = __builtin_bit_cast(uint32_t, h0);
+        p1[j] = __builtin_bit_cast(uint32_t, __builtin_convertvector(r, f16x2));
+    }
+}
+
 template <int KIND> struct PackTraits;
 template <> struct PackTraits<PK_F64> { typedef double S; static const int UE = 2; static const int ESZ = 8; static const int NP = 1; };
 template <> struct PackTraits<PK_F32> { typedef float S; static const int UE = 4; static const int ESZ = 4; static const int NP = 1; };
 template <> struct PackTraits<PK_B16> { typedef uint16_t S; static const int UE = 8; static const int ESZ = 2; static const int NP = 1; };
 template <> struct PackTraits<PK_SPLIT3> { typedef float S; static const int UE = 8; static const int ESZ = 2; static const int NP = 3; };
 template <> struct PackTraits<PK_FP8> { typedef float S; static const int UE = 16; static const int ESZ = 1; static const int NP = 2; };
+template <> struct PackTraits<PK_SPLIT2F16> { typedef float S; static const int UE = 8; static const int ESZ = 2; static const int NP = 2; };
 
 // Write one 16-byte unit (of each piece) of the packed image: row rr of
 // group grp, block kb, chunk ch, plane half, from the unit's values.
@@ -230,6 +252,12 @@ DEVI void pack_emit(const PackArgs &a, uint32_t grp, uint32_t kb, uint32_t ch, u
         }
         put(0, w0);
         if (a.refine) put(g.piece_bytes, w1);
+    } else if constexpr (KIND == PK_SPLIT2F16) {
+        const int e = rvalid ? row_scale_exp(((const uint32_t *)a.exps)[row]) : 0;
+        u32x4 w0, w1;
+        split2_f16_units(*(const float(*)[8])vals_f, e, w0, w1);
+        put(0, w0);
+        put(g.piece_bytes, w1);
     } else {   // PK_SPLIT3: a0 = bf16(a), a1 = bf16(a - a0), a2 = bf16(a - a0 - a1)
         float x[8];
 #pragma unroll
@@ -240,6 +268,72 @@ DEVI void pack_emit(const PackArgs &a, uint32_t grp, uint32_t kb, uint32_t ch, u
         put(g.piece_bytes, w1);
         put(2 * g.piece_bytes, w2);
     }
+}
+
+// Row amax of the two-piece FP16 split, K-major source: one wave per row,
+// 16-byte loads when VEC (ld % 4 == 0, 16-byte aligned base).  NaNs are
+// skipped (fmaxf); they reach the product through the values themselves.
+template <int VEC>
+__global__ __launch_bounds__(256) void row_amax_k_kernel(RowAmaxArgs a) {
+    const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row >= a.R) return;
+    const float *q = a.src + row * a.ld;
+    float m = 0.f;
+    int64_t k = 0;
+    if (VEC) {
+        const int64_t k4 = a.Kd / 4 * 4;
+#pragma unroll 4
+        for (k = lane * 4; k < k4; k += 256) {
+            const float4 v = *(const float4 *)(q + k);
+            m = fmaxf(m, fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
+        }
+        k = k4;
+    }
+    for (int64_t kk = k + lane; kk < a.Kd; kk += 64) m = fmaxf(m, fabsf(q[kk]));
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+    if (lane == 0) a.amax[row] = __float_as_uint(m);
+}
+
+// Row amax, MN-major source (element (kk, r) at src[kk ld + r]): thread
+// columns (4 per thread when VEC) over a slab of 256 contraction rows, then
+// one atomic max per column; the host zero-fills amax first.  Workgroup b
+// takes column block b % ncb of slab b / ncb.
+template <int VEC>
+__global__ __launch_bounds__(256) void row_amax_mn_kernel(RowAmaxArgs a) {
+    constexpr int CW = VEC ? 4 : 1;
+    const int64_t ncb = (a.R + 256 * CW - 1) / (256 * CW);
+    const int64_t r0 = ((int64_t)(blockIdx.x % ncb) * 256 + threadIdx.x) * CW;
+    if (r0 >= a.R) return;
+    const int64_t k0 = (int64_t)(blockIdx.x / ncb) * 256;
+    const int64_t k1 = k0 + 256 < a.Kd ? k0 + 256 : a.Kd;
+    float m[CW];
+#pragma unroll
+    for (int j = 0; j < CW; ++j) m[j] = 0.f;
+    bool done = false;
+    if constexpr (VEC) {
+        if (r0 + 3 < a.R) {
+#pragma unroll 4
+            for (int64_t kk = k0; kk < k1; ++kk) {
+                const float4 v = *(const float4 *)(a.src + kk * a.ld + r0);
+                m[0] = fmaxf(m[0], fabsf(v.x));
+                m[1] = fmaxf(m[1], fabsf(v.y));
+                m[2] = fmaxf(m[2], fabsf(v.z));
+                m[3] = fmaxf(m[3], fabsf(v.w));
+            }
+            done = true;
+        }
+    }
+    if (!done) {
+        for (int64_t kk = k0; kk < k1; ++kk)
+#pragma unroll
+            for (int j = 0; j < CW; ++j)
+                if (r0 + j < a.R) m[j] = fmaxf(m[j], fabsf(a.src[kk * a.ld + r0 + j]));
+    }
+#pragma unroll
+    for (int j = 0; j < CW; ++j)
+        if (r0 + j < a.R) atomicMax(a.amax + r0 + j, __float_as_uint(m[j]));
 }
 
 // An MN-major unit of pack_kernel's numbering: row rr of group grp, block
@@ -452,10 +546,13 @@ __global__ __launch_bounds__(256) void pack_kernel(PackArgs a) {
 // the hyper-systolic main loop on MFMA
 // ---------------------------------------------------------------------------
 // FORM 0: one piece per operand, one product.  FORM 1: three bf16 pieces,
-// the six products a_i b_j with i + j <= 2, smallest first.
+// the six products a_i b_j with i + j <= 2, smallest first.  FORM 2: two
+// f16 pieces of the row-scaled operands, the three products a_i b_j with
+// i + j <= 1, smallest first; the epilogue removes the row scales.
 template <int FORM> struct Form;
 template <> struct Form<0> { static const int NP = 1; static const int NPROD = 1; };
 template <> struct Form<1> { static const int NP = 3; static const int NPROD = 6; };
+template <> struct Form<2> { static const int NP = 2; static const int NPROD = 3; };
 
 template <int FAM> struct Mfma;
 template <> struct Mfma<FAM_F64> { static const int T = 16; typedef f64x4 Acc; };
@@ -464,7 +561,8 @@ template <> struct Mfma<FAM_BF16> { static const int T = 32; typedef f32x16 Acc;
 template <> struct Mfma<FAM_F16> { static const int T = 32; typedef f32x16 Acc; };
 template <> struct Mfma<FAM_FP8> { static const int T = 32; typedef f32x16 Acc; };
 
-// Pieces per operand: split-BF16 3, refined FP8 2 (q0, q1), otherwise 1.
+// Pieces per operand: split-BF16 3, two-piece FP16 2, refined FP8 2 (q0,
+// q1), otherwise 1.
 template <int FAM, int FORM>
 struct Pieces { static const int NP = FAM == FAM_FP8 ? (FORM ? 2 : 1) : Form<FORM>::NP; };
 
@@ -617,6 +715,14 @@ DEVI void mfma_row(AccRow &accr, const AV &av, const BV &bv) {
             for (int t = 0; t < 4; ++t)
                 accr[ni] = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(av[0][t]), __uint_as_float(bv[0][ni][t]),
                                                                accr[ni], 0, 0, 0);
+        } else if constexpr (FAM == FAM_F16 && FORM == 2) {
+            // a1 b0, a0 b1, a0 b0: smallest first
+            accr[ni] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, av[1]),
+                                                              __builtin_bit_cast(f16x8, bv[0][ni]), accr[ni], 0, 0, 0);
+            accr[ni] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, av[0]),
+                                                              __builtin_bit_cast(f16x8, bv[1][ni]), accr[ni], 0, 0, 0);
+            accr[ni] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, av[0]),
+                                                              __builtin_bit_cast(f16x8, bv[0][ni]), accr[ni], 0, 0, 0);
         } else if constexpr (FAM == FAM_F16) {
             accr[ni] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, av[0]),
                                                               __builtin_bit_cast(f16x8, bv[0][ni]), accr[ni], 0, 0, 0);
@@ -964,6 +1070,18 @@ void mm_kernel(MainArgs a) {
     // at a time (row index computed once, then its columns).
     const int64_t S_r = a.S_r;
     constexpr int NE = (int)(sizeof(Acc) / sizeof(acc[0][0][0]));
+    // two-piece FP16: the tile holds C' = sum a' b' of the scaled operands;
+    // C = C' 2^-(e_row + e_col) (exact unless the result is subnormal)
+    constexpr bool ROWSCALE = FAM == FAM_F16 && FORM == 2;
+    int ecol[C::TN];
+#pragma unroll
+    for (int ni = 0; ni < C::TN; ++ni) {
+        ecol[ni] = 0;
+        if constexpr (ROWSCALE) {
+            const int64_t col = ntile * BN + wn * C::WN + ni * C::MT + (lane & 31);
+            if (col < a.N) ecol[ni] = row_scale_exp(((const uint32_t *)a.b_exps)[col]);
+        }
+    }
 #pragma unroll
     for (int mi = 0; mi < C::TM; ++mi) {
 #pragma unroll
@@ -979,11 +1097,15 @@ void mm_kernel(MainArgs a) {
             const bool rok = i < ng && within < S_r && row < a.M;
             const int64_t cbase = ntile * BN + wn * C::WN + (FAM == FAM_F64 ? (lane & 15) : (lane & 31));
             const int64_t obase = row * a.ldo + cbase;
+            int erow = 0;
+            if constexpr (ROWSCALE) erow = rok ? row_scale_exp(((const uint32_t *)a.a_exps)[row]) : 0;
 #pragma unroll
             for (int ni = 0; ni < C::TN; ++ni) {
                 const bool ok = rok && cbase + ni * C::MT < a.N;
                 if (ok) {
                     if (a.out_f64) ((double *)a.out)[obase + ni * C::MT] = (double)acc[mi][ni][e];
+                    else if constexpr (ROWSCALE)
+                        ((float *)a.out)[obase + ni * C::MT] = ldexpf((float)acc[mi][ni][e], -(erow + ecol[ni]));
                     else ((float *)a.out)[obase + ni * C::MT] = (float)acc[mi][ni][e];
                 }
             }
@@ -1201,6 +1323,8 @@ hipError_t launch_pack(int kind, int kmajor, const PackArgs &a, hipStream_t st) 
         case PK_SPLIT3 * 2 + 1: HS_PACK(PK_SPLIT3, 1); break;
         case PK_FP8 * 2: HS_PACK(PK_FP8, 0); break;
         case PK_FP8 * 2 + 1: HS_PACK(PK_FP8, 1); break;
+        case PK_SPLIT2F16 * 2: HS_PACK(PK_SPLIT2F16, 0); break;
+        case PK_SPLIT2F16 * 2 + 1: HS_PACK(PK_SPLIT2F16, 1); break;
         default: return hipErrorInvalidValue;
     }
 #undef HS_PACK
@@ -1234,14 +1358,15 @@ int mm_chunks_per_stage(int fam, int form) {
     if (fam == FAM_F64) return 4;
     if (fam == FAM_FP8) return form == 1 ? 1 : 2;
     if (fam == FAM_F32) return 2;
-    return form == 1 ? 1 : 2;
+    return form == 1 ? 1 : 2;     // split-BF16 1; BF16, FP16, two-piece FP16 2
 }
 
 // 8 waves (2 per SIMD) for the 256 x 256 tiles, 4 for FP64's 64 x 64.
 hipError_t launch_mm(int fam, int form, const MainArgs &a, hipStream_t st) {
     if (fam == FAM_F64) return launch_mm_t<FAM_F64, 0, 64, 64, 4, 4>(a, st);
     if (fam == FAM_F32) return launch_mm_t<FAM_F32, 0, 256, 256, 2, 8>(a, st);
-    if (fam == FAM_F16) return launch_mm_t<FAM_F16, 0, 256, 256, 2, 8>(a, st);
+    if (fam == FAM_F16 && form == 0) return launch_mm_t<FAM_F16, 0, 256, 256, 2, 8>(a, st);
+    if (fam == FAM_F16 && form == 2) return launch_mm_t<FAM_F16, 2, 256, 256, 2, 8>(a, st);
     if (fam == FAM_BF16 && form == 0) return launch_mm_t<FAM_BF16, 0, 256, 256, 2, 8>(a, st);
     if (fam == FAM_BF16 && form == 1) return launch_mm_t<FAM_BF16, 1, 256, 256, 1, 8>(a, st);
     if (fam == FAM_FP8 && form == 0) return launch_mm_t<FAM_FP8, 0, 256, 256, 2, 8>(a, st);
@@ -1256,8 +1381,29 @@ hipError_t launch_pack_mn(int kind, const PackArgs &a, hipStream_t st) {
         case PK_F32: hipLaunchKernelGGL((pack_mn_kernel<PK_F32>), dim3(nb), dim3(256), 0, st, a); break;
         case PK_SPLIT3: hipLaunchKernelGGL((pack_mn_kernel<PK_SPLIT3>), dim3(nb), dim3(256), 0, st, a); break;
         case PK_FP8: hipLaunchKernelGGL((pack_mn_kernel<PK_FP8>), dim3(nb), dim3(256), 0, st, a); break;
+        case PK_SPLIT2F16: hipLaunchKernelGGL((pack_mn_kernel<PK_SPLIT2F16>), dim3(nb), dim3(256), 0, st, a); break;
         default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_zero(int f64, void *Cout, int64_t M, int64_t N, int64_t ldc, hipStream_t st);
+
+hipError_t launch_row_amax(const RowAmaxArgs &a, hipStream_t st) {
+    if (a.R == 0) return hipSuccess;
+    const bool vec = a.ld % 4 == 0 && ((uintptr_t)a.src % 16) == 0;
+    if (a.kmajor) {
+        const dim3 grid((unsigned)((a.R + 3) / 4));
+        if (vec) hipLaunchKernelGGL(row_amax_k_kernel<1>, grid, dim3(256), 0, st, a);
+        else hipLaunchKernelGGL(row_amax_k_kernel<0>, grid, dim3(256), 0, st, a);
+        return hipGetLastError();
+    }
+    hipError_t e = launch_fill_zero(0, a.amax, 1, a.R, a.R, st);   // zero bits = 0.0f
+    if (e != hipSuccess || a.Kd == 0) return e;
+    // R Kd < 2^34 (the packing limit), so blocks < 2^18
+    const int64_t slabs = (a.Kd + 255) / 256;
+    if (vec) hipLaunchKernelGGL(row_amax_mn_kernel<1>, dim3((unsigned)((a.R + 1023) / 1024 * slabs)), dim3(256), 0, st, a);
+    else hipLaunchKernelGGL(row_amax_mn_kernel<0>, dim3((unsigned)((a.R + 255) / 256 * slabs)), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 

@@ -14,7 +14,8 @@ except ImportError:  # pragma: no cover
     torch = None
 
 STORAGE = {"f64": "float64", "f32": "float32", "bf16": "bfloat16", "f16": "float16",
-           "split3_bf16": "float32", "fp8_e4m3": "float32", "fp8_e4m3_r1": "float32"}
+           "split3_bf16": "float32", "fp8_e4m3": "float32", "fp8_e4m3_r1": "float32",
+           "split2_f16": "float32"}
 
 
 def gpu_available():
@@ -46,7 +47,7 @@ def poisoned(shape, dtype, device="cuda"):
 # parity gates
 # ---------------------------------------------------------------------------
 # err_row (relative 2-norm per row): the stated tolerances of each form
-ROW_TOL = {"f64": 1e-12, "f32": 1e-5, "split3_bf16": 1e-5, "bf16": 1.5e-2, "f16": 3e-3,
+ROW_TOL = {"f64": 1e-12, "f32": 1e-5, "split3_bf16": 1e-5, "split2_f16": 1e-5, "bf16": 1.5e-2, "f16": 3e-3,
            "fp8_e4m3": 1e-1, "fp8_e4m3_r1": 1e-2, "c32": 1e-5, "c32_split3_bf16": 1e-5}
 # err_term (element error over u sqrt(k sum_t (a_t b_t)^2), the statistical
 # scale of a dot product's rounding errors) for the FP32-accurate and FP64
@@ -54,7 +55,7 @@ ROW_TOL = {"f64": 1e-12, "f32": 1e-5, "split3_bf16": 1e-5, "bf16": 1.5e-2, "f16"
 # measures 0.5 - 0.7 u; a lone wrong element is caught once its error
 # passes 16 u sqrt(k) of its own magnitude (8.6e-5 at k = 8192), where the
 # row gate needs 1e-5 sqrt(n) (9e-4 at n = 8192).
-TERM_C = {"f64": 16, "f32": 16, "split3_bf16": 16}
+TERM_C = {"f64": 16, "f32": 16, "split3_bf16": 16, "split2_f16": 16}
 # Element-wise bound |dC_ij| <= (c k + d) u (|A||B|)_ij, u the unit roundoff
 # of the accumulator (FP32 2^-24, FP64 2^-53), k the contraction length:
 #   * every product a_ik b_kj of the stored inputs enters one accumulator
@@ -68,9 +69,19 @@ TERM_C = {"f64": 16, "f32": 16, "split3_bf16": 16}
 #     3-piece split (each operand a = a0 + a1 + a2 + r, |r| <= u |a|):
 #     under 4.1 u per term, and the kept pieces' absolute sum exceeds
 #     |a||b| by at most 2^-6: (13 k + 5) u;
+#   * two-piece FP16 (products of the row-scaled operands, scaled back
+#     exactly): 3 products per term, so at most 3k additions (6 k u) on
+#     partial sums up to (1 + 2^-10) sum |a||b|; the representation
+#     a' = a0 + a1 + r with |r| <= 2^-22 |a'| (4 u) and the dropped a1 b1
+#     (|a1| <= 2^-11 |a'|: 4 u) leave at most 3 (4 u) + 4 u = 12 u per term
+#     (elements under 2^-17 of their row's max can carry a further absolute
+#     2^-39 of that max from a subnormal a1, far inside the margin of the
+#     round-up below): (7 k + 13) u;
 #   * complex forms run as a real product of contraction 2k.
-ELEM_C = {"f64": (3, 0), "f32": (3, 0), "bf16": (3, 0), "f16": (3, 0), "split3_bf16": (13, 5)}
-UNIT = {"f64": 2.0 ** -53, "f32": 2.0 ** -24, "bf16": 2.0 ** -24, "f16": 2.0 ** -24, "split3_bf16": 2.0 ** -24}
+ELEM_C = {"f64": (3, 0), "f32": (3, 0), "bf16": (3, 0), "f16": (3, 0), "split3_bf16": (13, 5),
+          "split2_f16": (7, 13)}
+UNIT = {"f64": 2.0 ** -53, "f32": 2.0 ** -24, "bf16": 2.0 ** -24, "f16": 2.0 ** -24, "split3_bf16": 2.0 ** -24,
+        "split2_f16": 2.0 ** -24}
 COMPLEX_BASE = {"c32": "f32", "c32_split3_bf16": "split3_bf16"}
 
 

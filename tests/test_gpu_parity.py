@@ -2,11 +2,12 @@
 
 Gates (tests/_gpu.py: ``check``):
   err_row  = max_r |C_r - Chat_r| / |Chat_r|:
-             f64 1e-12; f32, split3_bf16 1e-5; bf16 1.5e-2 and f16 3e-3
+             f64 1e-12; f32, split3_bf16, split2_f16 1e-5; bf16 1.5e-2 and
+             f16 3e-3
              (reported forms: the inputs' rounding is in the stored values)
   err_term = element error over u sqrt(k sum_t (a_t b_t)^2), the
              statistical scale of its rounding errors: f64, f32 and
-             split3_bf16 16 u (a lone wrong element is seen at its own scale,
+             the split forms 16 u (a lone wrong element is seen at its own scale,
              not diluted over a row)
   err_elem = max |dC| / (|A||B|) <= (c k + d) u, the worst-case rounding
              bound of each form's accumulation (derived beside ``elem_bound``)
@@ -56,7 +57,7 @@ SMALL = [
     (33, 17, 9, 4, 2),
     (520, 600, 264, 4, 2),
 ]
-DTYPES = ["f64", "f32", "split3_bf16", "bf16", "f16"]
+DTYPES = ["f64", "f32", "split3_bf16", "bf16", "f16", "split2_f16"]
 
 
 def _gemm_case(dt, m, n, k, p, K, tn, seed, gen=inputs.uniform):
@@ -136,7 +137,7 @@ def test_gemv(dt, shape, p, K):
     assert np.array_equal(host(yi), oracle.gemv(Ai64, xi64))
 
 
-@pytest.mark.parametrize("dt", ["f32", "split3_bf16", "bf16", "f16"])
+@pytest.mark.parametrize("dt", ["f32", "split3_bf16", "bf16", "f16", "split2_f16"])
 @pytest.mark.parametrize("K", [0, 2])
 def test_precision_config_n8192(dt, K):
     """n = 8192, p = 64, N(0, 1) rows scaled log-uniformly in [1e-3, 1e3]; 32 sampled rows."""
@@ -153,7 +154,7 @@ def test_precision_config_n8192(dt, K):
     check(got, ref, dt, A64[rows], B64, what="precision n=8192 K=%d" % K)
 
 
-@pytest.mark.parametrize("dt", ["split3_bf16", "f32"])
+@pytest.mark.parametrize("dt", ["split3_bf16", "f32", "split2_f16"])
 def test_headline_step_n8192(dt):
     """The benchmark's step exactly as bench.py times it: its own inputs
     (n = 8192, A and B row-scaled, G N(0, 1)), its step function (C = A.B,
@@ -174,7 +175,7 @@ def test_headline_step_n8192(dt):
     check(host(dB)[rows], oracle.grad_b_rows(A64, G64, rows), dt, A64[:, rows].T, G64, what="headline step dB")
 
 
-@pytest.mark.parametrize("dt", ["f32", "split3_bf16"])
+@pytest.mark.parametrize("dt", ["f32", "split3_bf16", "split2_f16"])
 def test_backward_config(dt):
     """A 4096 x 2048, B 2048 x 8192, G N(0, 1), p = 16: C, dA, dB on sampled rows."""
     _skip_no_gpu()
@@ -193,7 +194,7 @@ def test_backward_config(dt):
     check(host(dB)[rk], oracle.grad_b_rows(A64, G64, rk), dt, A64[:, rk].T, G64, what="C4 dB")
 
 
-@pytest.mark.parametrize("dt", DTYPES[:3])
+@pytest.mark.parametrize("dt", ["f64", "f32", "split3_bf16", "split2_f16"])
 @pytest.mark.parametrize("case", [(96, 80, 64, 8, 2), (200, 136, 152, 8, 4), (64, 64, 64, 16, 0)])
 def test_backward_small(dt, case):
     _skip_no_gpu()
@@ -250,7 +251,7 @@ def test_autograd_fd_fp64_64cubed():
             assert abs((lp - lm) / (2 * h) - an) <= 1e-9 * max(1.0, abs(an))
 
 
-@pytest.mark.parametrize("dt", ["f32", "split3_bf16"])
+@pytest.mark.parametrize("dt", ["f32", "split3_bf16", "split2_f16"])
 def test_autograd_matches_oracle(dt):
     _skip_no_gpu()
     m, k, n = 192, 160, 224
@@ -268,7 +269,7 @@ def test_autograd_matches_oracle(dt):
     check(host(B.grad), rB, dt, A64.T, G64, what="autograd dB")
 
 
-@pytest.mark.parametrize("dt", ["f32", "split3_bf16", "bf16"])
+@pytest.mark.parametrize("dt", ["f32", "split3_bf16", "bf16", "split2_f16"])
 def test_bitwise_deterministic(dt):
     _skip_no_gpu()
     A, _ = to_dev(inputs.normal((1024, 768), seed=81), dt)
@@ -283,7 +284,7 @@ def test_bitwise_deterministic(dt):
 def test_empty_and_zero_contraction():
     _skip_no_gpu()
     note("empty shapes")
-    for dt in ["f32", "f64", "split3_bf16"]:
+    for dt in ["f32", "f64", "split3_bf16", "split2_f16"]:
         A, _ = to_dev(np.zeros((0, 5)), dt)
         B, _ = to_dev(np.zeros((5, 7)), dt)
         assert hs.hs_gemm(A, B, dtype=dt, p=4).shape == (0, 7)
@@ -301,7 +302,7 @@ def test_empty_and_zero_contraction():
 def test_leading_dimension_views():
     """Row strides larger than the row length (sub-matrix views)."""
     _skip_no_gpu()
-    for dt in ["f32", "split3_bf16", "f64"]:
+    for dt in ["f32", "split3_bf16", "f64", "split2_f16"]:
         Abig, Abig64 = to_dev(inputs.normal((130, 300), seed=91), dt)
         Bbig, Bbig64 = to_dev(inputs.normal((200, 170), seed=92), dt)
         A, B = Abig[:, 10:210], Bbig[:, 3:163]
@@ -426,25 +427,25 @@ def _strided(x64, dt, pad=1):
     return t[:, :c]
 
 
+@pytest.mark.parametrize("dt", ["split3_bf16", "split2_f16"])
 @pytest.mark.parametrize("case", PACK_LOAD_CASES)
-def test_split_pack_load_paths(case):
-    """The split form on contiguous sources against the oracle, and bit for
+def test_split_pack_load_paths(dt, case):
+    """The split forms on contiguous sources against the oracle, and bit for
     bit against the same values read through odd row strides, for C = A.B,
     A^T.B and the backward pair (both source orientations of both
-    operands)."""
+    operands; for the two-piece FP16 form also both row-amax kernels)."""
     _skip_no_gpu()
-    dt = "split3_bf16"
     m, n, k, p, K = case
     A, A64 = to_dev(inputs.row_scaled((m, k), seed=1601), dt)
     At, At64 = to_dev(np.ascontiguousarray(A64.T), dt)
     B_, B64 = to_dev(inputs.row_scaled((k, n), seed=1602), dt)
     G, G64 = to_dev(inputs.normal((m, n), seed=1603), dt)
     Av, Atv, Bv, Gv = _strided(A64, dt), _strided(At64, dt, 3), _strided(B64, dt), _strided(G64, dt, 2)
-    note("split contiguous", case)
+    note("split contiguous", dt, case)
     C = hs.hs_gemm(A, B_, dtype=dt, p=p, K=K)
     Ct = hs.hs_gemm_tn(At, B_, dtype=dt, p=p, K=K)
     dA, dB = hs.hs_gemm_backward(A, B_, G, dtype=dt, p=p, K=K)
-    note("split strided", case)
+    note("split strided", dt, case)
     Cp = hs.hs_gemm(Av, Bv, dtype=dt, p=p, K=K)
     Ctp = hs.hs_gemm_tn(Atv, Bv, dtype=dt, p=p, K=K)
     dAp, dBp = hs.hs_gemm_backward(Av, Bv, Gv, dtype=dt, p=p, K=K)
@@ -495,6 +496,70 @@ def test_split3_pieces_reconstruct_exactly_backward(p):
     dA, dB = hs.hs_gemm_backward(DA, DB, G, dtype="split3_bf16", p=p, K=1)
     assert np.array_equal(host(dA), Gf * db[None, :])
     assert np.array_equal(host(dB), da[:, None] * Gf)
+
+
+@pytest.mark.parametrize("tn", [False, True])
+@pytest.mark.parametrize("p", [4, 3])
+def test_split2_pieces_bit_exact(tn, p):
+    """The two-piece FP16 form's pieces and row scales, bit for bit against
+    oracle.precision: C = A . D with D a diagonal of signed powers of two is
+    exactly (a0 + a1) 2^-e d (D's rows scale to 2^14 exactly, one nonzero
+    product per output), the value the oracle assigns to each element; the
+    same on the travelling side (D . B, scales per column of B)."""
+    from oracle import precision as P
+    _skip_no_gpu()
+    dt = "split2_f16"
+    m, k = 200, 320
+    A, Af = to_dev(inputs.row_scaled((k, m) if tn else (m, k), seed=911), dt)
+    D64, d = _pow2_diag(k, 912)
+    D, _ = to_dev(D64, dt)
+    note("split2 pieces, static side, tn=%s p=%d" % (tn, p))
+    C = (hs.hs_gemm_tn if tn else hs.hs_gemm)(A, D, dtype=dt, p=p, K=2 if p % 2 == 0 else 1)
+    Aop = Af.T if tn else Af                       # the operand as it multiplies
+    assert np.array_equal(host(C), P.split2_f16_value(Aop) * d[None, :])
+    B, Bf = to_dev(inputs.row_scaled((k, m), seed=913), dt)
+    note("split2 pieces, travelling side, tn=%s p=%d" % (tn, p))
+    C2 = (hs.hs_gemm_tn if tn else hs.hs_gemm)(D, B, dtype=dt, p=p, K=2 if p % 2 == 0 else 1)
+    assert np.array_equal(host(C2), d[:, None] * P.split2_f16_value(Bf, row_axis=1))
+
+
+@pytest.mark.parametrize("p", [4, 3])
+def test_split2_pieces_bit_exact_backward(p):
+    """dA = G . B^T with B diagonal (G's rows scaled and split), dB = A^T . G
+    with A diagonal (G's columns scaled and split)."""
+    from oracle import precision as P
+    _skip_no_gpu()
+    dt = "split2_f16"
+    n = 256
+    G, Gf = to_dev(inputs.row_scaled((n, n), seed=914), dt)
+    DA64, da = _pow2_diag(n, 915)
+    DB64, db = _pow2_diag(n, 916)
+    DA, _ = to_dev(DA64, dt)
+    DB, _ = to_dev(DB64, dt)
+    note("split2 pieces, backward p=%d" % p)
+    dA, dB = hs.hs_gemm_backward(DA, DB, G, dtype=dt, p=p, K=1)
+    assert np.array_equal(host(dA), P.split2_f16_value(Gf) * db[None, :])
+    assert np.array_equal(host(dB), da[:, None] * P.split2_f16_value(Gf, row_axis=1))
+
+
+def test_split2_extreme_row_scales():
+    """Rows spanning 2^-100 .. 2^100 (each row scaled to its own range) and
+    a zero row: every row at FP32 accuracy, the zero row exactly zero."""
+    _skip_no_gpu()
+    dt = "split2_f16"
+    m, n, k = 96, 80, 512
+    g = np.random.default_rng(917)
+    A64 = g.standard_normal((m, k)) * 2.0 ** g.integers(-100, 101, (m, 1))
+    A64[7] = 0.0
+    B64 = g.standard_normal((k, n)) * 2.0 ** g.integers(-20, 21, (1, n))
+    A, Af = to_dev(A64, dt)
+    B, Bf = to_dev(B64, dt)
+    note("split2 extreme row scales")
+    C = hs.hs_gemm(A, B, dtype=dt, p=4, K=2)
+    torch.cuda.synchronize()
+    got = host(C)
+    check(got, oracle.gemm(Af, Bf), dt, Af, Bf, what="split2 extreme rows")
+    assert not got[7].any()
 
 
 @pytest.mark.parametrize("dt", FP8)

@@ -39,13 +39,13 @@ def _schedule(g, max_p=24):
     return p, int(divs[int(g.integers(0, len(divs)))])
 
 
-def _case(seed):
+def _case(seed, form=None):
     g = inputs.rng(31000 + seed)
     m, n, k = (int(x) for x in g.integers(1, 400, size=3))
     p, K = _schedule(g)
     dt = DTYPES[int(g.integers(0, len(DTYPES)))]
     ints = bool(g.integers(0, 4) == 0)
-    return g, m, n, k, p, K, dt, ints
+    return g, m, n, k, p, K, form or dt, ints
 
 
 def _out_dtype(dt):
@@ -55,8 +55,19 @@ def _out_dtype(dt):
 @pytest.mark.parametrize("seed", range(48))
 def test_random_products(seed):
     """C = A.B, C = A^T.B and the backward pair on one random case."""
+    _random_products(seed)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_products_split2_f16(seed):
+    """The same draws (shapes, schedules, small-integer cases) in the
+    two-piece FP16 form."""
+    _random_products(100 + seed, "split2_f16")
+
+
+def _random_products(seed, form=None):
     _skip_no_gpu()
-    g, m, n, k, p, K, dt, ints = _case(seed)
+    g, m, n, k, p, K, dt, ints = _case(seed, form)
 
     def taken(m, n, k, p, K):
         return all(B.hs_workspace_size(op, a, b, c, dt, p, K) != B.SIZE_MAX

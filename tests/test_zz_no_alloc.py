@@ -23,7 +23,7 @@ def _skip_no_gpu():
         pytest.skip("no GPU")
 
 
-@pytest.mark.parametrize("dt", ["split3_bf16", "f32", "f64", "fp8_e4m3_r1"])
+@pytest.mark.parametrize("dt", ["split3_bf16", "f32", "f64", "fp8_e4m3_r1", "split2_f16"])
 def test_noalloc_equals_gemm_two_calls(dt):
     _skip_no_gpu()
     fp8 = dt.startswith("fp8")
