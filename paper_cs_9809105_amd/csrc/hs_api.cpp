@@ -85,7 +85,13 @@ struct Plan {
     int64_t a_span;                   // bytes of a workgroup's static-operand region
     size_t off_ea, off_eb;            // fp8: tile exponents of each operand
     int64_t tiles_k, tiles_ra, tiles_rb;
+    int nsplit, split_stages;         // workgroups per output tile, stages each
+    size_t off_part;                  // their partial planes (nsplit > 1)
 };
+
+// Compute units of the MI355X: a launch with fewer output tiles than this
+// leaves CUs idle unless each tile's stage sequence is split.
+const int64_t kCUs = 256;
 
 // Threads of the pack kernel: one per 16-byte unit; a K-major source is
 // walked in 8 x 8 (row, unit) blocks, so both counts round up to 8.
@@ -160,9 +166,22 @@ hs_status make_plan(int64_t M, int64_t N, int64_t Kd, int dt, hs_schedule s, Pla
     if (pack_units(a, 1) >= (int64_t)1 << 31 || pack_units(b, 1) >= (int64_t)1 << 31) return HS_ERR_NOT_SUPPORTED;
     if ((int64_t)p * nch >= (int64_t)1 << 31) return HS_ERR_NOT_SUPPORTED;
 
+    // Output tiles under the CU count: split each tile's step order over
+    // nsplit workgroups (at most 4, at least 64 stages each), whose sums a
+    // fixed-order FP64 pass adds (the planes below)
+    {
+        const int64_t nstages = (int64_t)p * (nch / CPS);
+        const int64_t tiles = (int64_t)P->K * ceil_div(P->Kt, P->G) * a.GS * b.GS;
+        int64_t ns = 1;
+        if (tiles > 0 && tiles < kCUs) ns = std::min<int64_t>({4, kCUs / tiles, nstages / 64});
+        if (ns < 2) ns = 1;
+        P->split_stages = (int)ceil_div(nstages, ns);
+        P->nsplit = (int)ceil_div(nstages, P->split_stages);
+    }
+
     // workspace: the two packed operands (no partial planes: the collector
     // keeps every partial in registers), the FP8 tile exponents or the
-    // two-piece FP16 row amaxes
+    // two-piece FP16 row amaxes, and the split planes
     size_t off = 0;
     P->off_a = off; off = align_up(off + (size_t)(a.n_groups * a.group_bytes));
     P->off_b = off; off = align_up(off + (size_t)(b.n_groups * b.group_bytes));
@@ -178,6 +197,8 @@ hs_status make_plan(int64_t M, int64_t N, int64_t Kd, int dt, hs_schedule s, Pla
         P->off_ea = off; off = align_up(off + (size_t)M * sizeof(uint32_t));
         P->off_eb = off; off = align_up(off + (size_t)N * sizeof(uint32_t));
     }
+    P->off_part = off;
+    if (P->nsplit > 1) off = align_up(off + (size_t)P->nsplit * M * N * (P->f.out_f64 ? 8 : 4));
     P->total = (M == 0 || N == 0 || Kd == 0) ? 0 : off;
     return HS_OK;
 }
@@ -283,6 +304,9 @@ hs_status run_product(const Plan &P, const Operand &X, const Operand &Y, void *o
     m.out = out;
     m.ldo = ldo;
     m.n_ntiles = P.gb.GS;
+    m.nsplit = P.nsplit;
+    m.split_stages = P.split_stages;
+    m.part = w + P.off_part;
     {   // 32 workgroups per XCD: grp_v class members x grp_t column tiles
         const int64_t nt = P.gb.GS;
         int64_t gt = 1;
@@ -305,6 +329,8 @@ hs_status run_product(const Plan &P, const Operand &X, const Operand &Y, void *o
         (void)hipEventRecord(ev1, stream);
         g_events.push_back({ev0, ev1});
     }
+    if (e == hipSuccess && P.nsplit > 1)   // C = the planes' sum, fixed order, FP64
+        e = launch_backshift(f64, m.part, P.M * P.N, P.nsplit, P.M, P.N, out, ldo, stream);
     return launch_status(e);
 }
 

@@ -138,6 +138,12 @@ struct MainArgs {
     int out_f64;             // out element type: 1 double, 0 float
     // workgroup groups: grp_v class members x grp_t column tiles run together
     int64_t grp_v, grp_t, n_ug, n_tg;
+    // launches with fewer output tiles than CUs: nsplit workgroups per tile,
+    // each over split_stages consecutive stages of the step order, their sums
+    // in planes [nsplit][M][N] of part (element type as out), summed after
+    int nsplit;
+    int split_stages;
+    void *part;
 };
 
 struct GemvArgs {

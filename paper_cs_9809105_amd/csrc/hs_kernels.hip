@@ -822,11 +822,17 @@ void mm_kernel(MainArgs a) {
     // workgroups (one per CU of the XCD) take G_V members of one class times
     // G_T column tiles, so the XCD's L2 serves each travelling tile to G_V
     // workgroups and each static tile to G_T of them.
+    // With a.nsplit > 1 (launches with fewer output tiles than CUs) the grid
+    // holds nsplit copies of the tile grid; copy q walks only stages
+    // [q per, (q + 1) per) of the step order and leaves its sums in plane q
+    // of a.part (a fixed-order FP64 sum of the planes follows).
     int64_t bid = blockIdx.x;
     {
         const int64_t nwg = gridDim.x, xcd = bid % 8, per = nwg / 8, rem = nwg % 8;
         bid = xcd * per + (xcd < rem ? xcd : rem) + bid / 8;
     }
+    const int split = (int)(bid / (gridDim.x / a.nsplit));
+    bid %= gridDim.x / a.nsplit;
     const int p = a.p, K = a.K, Kt = a.Kt, MS = a.MS, G = a.G;
     int64_t ntile, msub;
     int c_class, r0, ng;
@@ -848,7 +854,9 @@ void mm_kernel(MainArgs a) {
 
     const int64_t nch = a.nch;
     const int spb = (int)(nch / CPS);                   // stages per contraction block
-    const int nstages = p * spb;                        // host keeps this below 2^31
+    // this workgroup's stages of the p spb (< 2^31, host) of the step order
+    const int s_begin = split * a.split_stages;
+    const int nstages = p * spb - s_begin < a.split_stages ? p * spb - s_begin : a.split_stages;
 
     // Each workgroup addresses its own region of the packed operands with
     // 32-bit offsets: for the static operand the G groups msub of stripes
@@ -905,7 +913,16 @@ void mm_kernel(MainArgs a) {
         ++q.t;
         q.kb = (c_class + K - 1 - q.t) % K;
     };
-    const Pos start{(c_class + K - 1) % K, 0, 0, 0, 0};
+    // position of stage s_begin: partial t, step j, stage cs of the block
+    Pos start;
+    {
+        const int per_t = Kt * spb;
+        start.t = s_begin / per_t;
+        start.j = (s_begin % per_t) / spb;
+        start.cs = s_begin % spb;
+        start.kb = (c_class + K - 1 - start.t) % K + start.j * K;
+        start.n = 0;
+    }
     const uint32_t a_stage = (uint32_t)(MS * C::CB), b_stage = (uint32_t)(BN * C::CB);
     // first chunk of the stage at q, then advance q by one stage
     auto next_chunk = [&](Pos &q) -> uint32_t {
@@ -1096,17 +1113,20 @@ void mm_kernel(MainArgs a) {
             const int64_t row = (int64_t)(r0 + i * K) * S_r + within;
             const bool rok = i < ng && within < S_r && row < a.M;
             const int64_t cbase = ntile * BN + wn * C::WN + (FAM == FAM_F64 ? (lane & 15) : (lane & 31));
-            const int64_t obase = row * a.ldo + cbase;
             int erow = 0;
             if constexpr (ROWSCALE) erow = rok ? row_scale_exp(((const uint32_t *)a.a_exps)[row]) : 0;
+            // the element's destination: C, or plane `split` of a.part (rows of N)
+            const bool to_part = a.nsplit > 1;
+            const int64_t obase = to_part ? ((int64_t)split * a.M + row) * a.N + cbase : row * a.ldo + cbase;
+            void *dst = to_part ? a.part : a.out;
 #pragma unroll
             for (int ni = 0; ni < C::TN; ++ni) {
                 const bool ok = rok && cbase + ni * C::MT < a.N;
                 if (ok) {
-                    if (a.out_f64) ((double *)a.out)[obase + ni * C::MT] = (double)acc[mi][ni][e];
+                    if (a.out_f64) ((double *)dst)[obase + ni * C::MT] = (double)acc[mi][ni][e];
                     else if constexpr (ROWSCALE)
-                        ((float *)a.out)[obase + ni * C::MT] = ldexpf((float)acc[mi][ni][e], -(erow + ecol[ni]));
-                    else ((float *)a.out)[obase + ni * C::MT] = (float)acc[mi][ni][e];
+                        ((float *)dst)[obase + ni * C::MT] = ldexpf((float)acc[mi][ni][e], -(erow + ecol[ni]));
+                    else ((float *)dst)[obase + ni * C::MT] = (float)acc[mi][ni][e];
                 }
             }
         }
@@ -1345,7 +1365,7 @@ static hipError_t launch_mm_t(const MainArgs &a, hipStream_t st) {
         if (e != hipSuccess) return e;
         if (dev >= 0 && dev < 64) attr_set[dev] = true;
     }
-    const int64_t nwg = (int64_t)a.K * a.n_ug * a.n_tg * a.grp_v * a.grp_t;
+    const int64_t nwg = (int64_t)a.K * a.n_ug * a.n_tg * a.grp_v * a.grp_t * a.nsplit;
     hipLaunchKernelGGL((mm_kernel<FAM, FORM, BM, BN, CPS, WAVES>), dim3((unsigned)nwg), dim3(C::NT), C::LDS_BYTES, st, a);
     return hipGetLastError();
 }

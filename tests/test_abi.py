@@ -411,3 +411,17 @@ def test_noalloc_rejects_before_any_launch():
     assert L.hs_gemm_noalloc(8, 8, 8, 99, s, FAKE, 8, FAKE, 8, FAKE, 8, None) == B.HS_ERR_NOT_SUPPORTED
     assert L.hs_gemm_noalloc(8, 8, 8, B.HS_F32, s, FAKE, 4, FAKE, 8, FAKE, 8, None) == B.HS_ERR_INVALID_VALUE
     assert B.hs_status_string(B.HS_ERR_EXCEEDS_SCRATCH).startswith("HS_ERR_EXCEEDS_SCRATCH")
+
+
+def test_split_planes_in_workspace():
+    """One 256 x 256 output tile pair (p = 4, K = 2: two classes) over a long
+    contraction splits each tile's 1024 stages over 4 workgroups, whose FP32
+    planes (4 x 256 x 256 x 4 bytes) join the packed operands (16 MiB each:
+    4 stripes x 4 blocks x 512 chunks x 64 rows x 32 bytes, and 4 blocks x
+    512 chunks x 256 columns x 32 bytes); with 64 stages (k = 1024) there is
+    no split and the workspace is the packed operands alone (1 MiB each)."""
+    ws = B.hs_workspace_size
+    assert ws(B.HS_OP_GEMM, 256, 256, 16384, "f32", 4, 2) == 32 * 2 ** 20 + 4 * 256 * 256 * 4
+    assert ws(B.HS_OP_GEMM, 256, 256, 1024, "f32", 4, 2) == 2 * 2 ** 20
+    # 1024 output tiles (n = 8192): no split, operands only
+    assert ws(B.HS_OP_GEMM, 8192, 8192, 8192, "f32", 64, 2) == 2 * 8192 * 8192 * 4

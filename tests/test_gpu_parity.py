@@ -314,6 +314,39 @@ def test_leading_dimension_views():
         check(host(C), ref, dt, Abig64[:, 10:210], Bbig64[:, 3:163], what="views")
 
 
+# Launches with fewer output tiles than CUs split each tile's step order over
+# up to 4 workgroups (each at least 64 stages) and sum their planes in FP64:
+# long contractions on one or a few tiles.
+SPLIT_CASES = [(256, 256, 16384, 4, 2), (300, 200, 8192, 8, 4), (512, 256, 6144, 3, 1), (64, 96, 4096, 16, 16)]
+
+
+@pytest.mark.parametrize("dt", ["f32", "split3_bf16", "split2_f16", "bf16", "f64"])
+@pytest.mark.parametrize("case", SPLIT_CASES)
+def test_split_stage_sequence(dt, case):
+    """C = A.B, A^T.B and the backward pair where the stage sequence is split
+    (tests/test_abi.py checks that such shapes take the split), against the
+    oracle; small integers bit for bit; run to run bitwise."""
+    _skip_no_gpu()
+    m, n, k, p, K = case
+    got, ref, A64, B64 = _gemm_case(dt, m, n, k, p, K, False, seed=1700 + m)
+    check(got, ref, dt, A64, B64, what="split stages %s" % (case,))
+    got_t, ref_t, At64, Bt64 = _gemm_case(dt, m, n, k, p, K, True, seed=1710 + m)
+    check(got_t, ref_t, dt, At64.T, Bt64, what="split stages tn %s" % (case,))
+    A, A64 = to_dev(inputs.normal((m, k), seed=1720), dt)
+    B, B64 = to_dev(inputs.normal((k, n), seed=1721), dt)
+    G, G64 = to_dev(inputs.normal((m, n), seed=1722), dt)
+    note("split stages backward", dt, case)
+    dA, dB = hs.hs_gemm_backward(A, B, G, dtype=dt, p=p, K=K)
+    dA2, dB2 = hs.hs_gemm_backward(A, B, G, dtype=dt, p=p, K=K)
+    torch.cuda.synchronize()
+    assert torch.equal(dA, dA2) and torch.equal(dB, dB2)
+    rA, rB = oracle.backward(A64, B64, G64)
+    check(host(dA), rA, dt, G64, B64.T, what="split stages dA %s" % (case,))
+    check(host(dB), rB, dt, A64.T, G64, what="split stages dB %s" % (case,))
+    got_i, ref_i, _, _ = _gemm_case(dt, m, n, k, p, K, False, seed=1730, gen=inputs.small_int)
+    assert np.array_equal(got_i, ref_i)
+
+
 def test_many_virtual_processors():
     """p = 256 (K = 16) and p = 4096 (K = 64) on small matrices."""
     _skip_no_gpu()
