@@ -275,9 +275,11 @@ hs_status hs_gemm_noalloc(int64_t m, int64_t n, int64_t k, int dtype, hs_schedul
 /* Kernel timing for measurement.  Between hs_profile_begin() and
  * hs_profile_end(), every launch of the main kernel of any call made from
  * this process (the MFMA kernel of a product, the matrix-vector kernel of
- * hs_gemv, the interaction kernel of hs_nbody) is bracketed by a pair of HIP events on its stream.
- * hs_profile_end() waits for those events and returns the summed elapsed
- * milliseconds and the number of launches.  Not thread-safe; host only.
+ * hs_gemv, the interaction kernel of hs_nbody) carries a pair of HIP events
+ * that its dispatch records itself (hipExtLaunchKernel), so they time the
+ * kernel's execution alone.  hs_profile_end() waits for those events and
+ * returns the summed elapsed milliseconds and the number of launches.  Not
+ * thread-safe, not for use under stream capture; host only.
  * Returns HS_ERR_INVALID_VALUE if profiling was not begun. */
 hs_status hs_profile_begin(void);
 hs_status hs_profile_end(double *total_ms, int64_t *launches);

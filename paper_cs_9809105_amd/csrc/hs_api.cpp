@@ -25,6 +25,8 @@ hipError_t launch_fill_zero(int f64, void *Cout, int64_t M, int64_t N, int64_t l
 hipError_t launch_gemv(int f64, const GemvArgs &a, hipStream_t st);
 hipError_t launch_fp8_exps(const Fp8ExpArgs &a, int64_t tiles, hipStream_t st);
 hipError_t launch_row_amax(const RowAmaxArgs &a, hipStream_t st);
+void set_timed_launch(hipEvent_t start, hipEvent_t stop);
+bool timed_launch_done();
 hipError_t launch_nbody(int f64, const void *bodies, void *out, const NbodyArgs &a, int kr, hipStream_t st);
 int mm_tile_rows(int fam);
 int mm_tile_cols(int fam);
@@ -211,6 +213,28 @@ bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
 bool g_prof = false;
 std::vector<std::pair<hipEvent_t, hipEvent_t>> g_events;
 
+// Two new events handed to the next timed launch, which records them itself.
+bool timing_events(hipEvent_t *ev0, hipEvent_t *ev1) {
+    if (hipEventCreate(ev0) != hipSuccess) return false;
+    if (hipEventCreate(ev1) != hipSuccess) {
+        (void)hipEventDestroy(*ev0);
+        return false;
+    }
+    set_timed_launch(*ev0, *ev1);
+    return true;
+}
+
+// After the launch call: keep the pair if a kernel took it (an empty
+// problem launches nothing), else release it.
+void keep_timing(hipEvent_t ev0, hipEvent_t ev1) {
+    if (timed_launch_done()) {
+        g_events.push_back({ev0, ev1});
+    } else {
+        (void)hipEventDestroy(ev0);
+        (void)hipEventDestroy(ev1);
+    }
+}
+
 struct Operand {
     const void *ptr;
     int64_t ld;
@@ -319,16 +343,9 @@ hs_status run_product(const Plan &P, const Operand &X, const Operand &Y, void *o
         m.n_ug = ceil_div(members, gv);
     }
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    if (g_prof) {
-        if (hipEventCreate(&ev0) != hipSuccess || hipEventCreate(&ev1) != hipSuccess)
-            return HS_ERR_LAUNCH_FAILED;
-        (void)hipEventRecord(ev0, stream);
-    }
+    if (g_prof && !timing_events(&ev0, &ev1)) return HS_ERR_LAUNCH_FAILED;
     e = launch_mm(P.f.fam, P.f.form, m, stream);
-    if (g_prof) {
-        (void)hipEventRecord(ev1, stream);
-        g_events.push_back({ev0, ev1});
-    }
+    if (g_prof) keep_timing(ev0, ev1);
     if (e == hipSuccess && P.nsplit > 1)   // C = the planes' sum, fixed order, FP64
         e = launch_backshift(f64, m.part, P.M * P.N, P.nsplit, P.M, P.N, out, ldo, stream);
     return launch_status(e);
@@ -562,16 +579,9 @@ hs_status hs_gemv(int64_t m, int64_t n, int dtype, hs_schedule s,
     const int VE = (f64 || cplx) ? 2 : 4;         // elements per 16-byte load
     g.vec = (g.S_k % VE == 0 && lda % VE == 0 && n % VE == 0 && aligned(A, 16) && aligned(x, 16)) ? 1 : 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    if (g_prof) {
-        if (hipEventCreate(&ev0) != hipSuccess || hipEventCreate(&ev1) != hipSuccess)
-            return HS_ERR_LAUNCH_FAILED;
-        (void)hipEventRecord(ev0, st);
-    }
+    if (g_prof && !timing_events(&ev0, &ev1)) return HS_ERR_LAUNCH_FAILED;
     hipError_t e = launch_gemv(f64, g, st);
-    if (g_prof) {
-        (void)hipEventRecord(ev1, st);
-        g_events.push_back({ev0, ev1});
-    }
+    if (g_prof) keep_timing(ev0, ev1);
     return launch_status(e);
 }
 
@@ -648,16 +658,9 @@ hs_status hs_nbody(int64_t n, int dtype, hs_schedule s, const void *bodies, doub
     hipStream_t st = (hipStream_t)stream;
     void *dst = a.K > 1 ? ws : out;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    if (g_prof) {
-        if (hipEventCreate(&ev0) != hipSuccess || hipEventCreate(&ev1) != hipSuccess)
-            return HS_ERR_LAUNCH_FAILED;
-        (void)hipEventRecord(ev0, st);
-    }
+    if (g_prof && !timing_events(&ev0, &ev1)) return HS_ERR_LAUNCH_FAILED;
     hipError_t e = launch_nbody(f64, bodies, dst, a, kr, st);
-    if (g_prof) {
-        (void)hipEventRecord(ev1, st);
-        g_events.push_back({ev0, ev1});
-    }
+    if (g_prof) keep_timing(ev0, ev1);
     if (e != hipSuccess) return HS_ERR_LAUNCH_FAILED;
     if (a.K > 1) return launch_status(launch_backshift(f64, ws, 4 * n, a.K, n, 4, out, 4, st));
     return HS_OK;

@@ -24,6 +24,7 @@
 //   gemv_kernel      y = A x with the same index map, collector form: one
 //                    wave owns a row and combines the K partial dot products
 //                    in the back-shift order (gemv_c32_kernel: complex64).
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -1328,6 +1329,41 @@ __global__ __launch_bounds__(256) void gemv_c32_kernel(GemvArgs a) {
 // ---------------------------------------------------------------------------
 static inline unsigned nblocks(int64_t work) { return (unsigned)((work + 255) / 256); }
 
+// Events of the next timed launch (hs_profile_begin / hs_profile_end): the
+// dispatch itself records them (hipExtLaunchKernel), so they bracket the
+// kernel's execution alone, without the gaps that separate event records
+// add around a short kernel.
+static hipEvent_t g_timed_start = nullptr, g_timed_stop = nullptr;
+static bool g_timed_used = false;
+void set_timed_launch(hipEvent_t start, hipEvent_t stop) {
+    g_timed_start = start;
+    g_timed_stop = stop;
+    g_timed_used = false;
+}
+bool take_timed_launch(hipEvent_t *start, hipEvent_t *stop) {
+    if (!g_timed_start) return false;
+    *start = g_timed_start;
+    *stop = g_timed_stop;
+    g_timed_start = g_timed_stop = nullptr;
+    g_timed_used = true;
+    return true;
+}
+// true if the events set last were taken by a launch; clears them
+bool timed_launch_done() {
+    const bool used = g_timed_used;
+    g_timed_start = g_timed_stop = nullptr;
+    g_timed_used = false;
+    return used;
+}
+#define HS_LAUNCH_TIMED(KERNEL, GRID, BLOCK, SHM, ST, ...)                                    \
+    do {                                                                                     \
+        hipEvent_t ts_, te_;                                                                 \
+        if (take_timed_launch(&ts_, &te_))                                                   \
+            hipExtLaunchKernelGGL(KERNEL, GRID, BLOCK, SHM, ST, ts_, te_, 0, __VA_ARGS__);   \
+        else                                                                                 \
+            hipLaunchKernelGGL(KERNEL, GRID, BLOCK, SHM, ST, __VA_ARGS__);                   \
+    } while (0)
+
 hipError_t launch_pack(int kind, int kmajor, const PackArgs &a, hipStream_t st) {
     if (a.total_units == 0) return hipSuccess;
     const unsigned nb = nblocks(a.total_units);
@@ -1366,7 +1402,7 @@ static hipError_t launch_mm_t(const MainArgs &a, hipStream_t st) {
         if (dev >= 0 && dev < 64) attr_set[dev] = true;
     }
     const int64_t nwg = (int64_t)a.K * a.n_ug * a.n_tg * a.grp_v * a.grp_t * a.nsplit;
-    hipLaunchKernelGGL((mm_kernel<FAM, FORM, BM, BN, CPS, WAVES>), dim3((unsigned)nwg), dim3(C::NT), C::LDS_BYTES, st, a);
+    HS_LAUNCH_TIMED((mm_kernel<FAM, FORM, BM, BN, CPS, WAVES>), dim3((unsigned)nwg), dim3(C::NT), C::LDS_BYTES, st, a);
     return hipGetLastError();
 }
 
@@ -1474,14 +1510,14 @@ hipError_t launch_gemv(int f64, const GemvArgs &a, hipStream_t st) {
     const unsigned nb = (unsigned)((a.m + 3) / 4);
     if (nb == 0) return hipSuccess;
     if (a.cplx) {
-        if (a.vec) hipLaunchKernelGGL((gemv_c32_kernel<2>), dim3(nb), dim3(256), 0, st, a);
-        else hipLaunchKernelGGL((gemv_c32_kernel<1>), dim3(nb), dim3(256), 0, st, a);
+        if (a.vec) HS_LAUNCH_TIMED((gemv_c32_kernel<2>), dim3(nb), dim3(256), 0, st, a);
+        else HS_LAUNCH_TIMED((gemv_c32_kernel<1>), dim3(nb), dim3(256), 0, st, a);
     } else if (f64) {
-        if (a.vec) hipLaunchKernelGGL((gemv_kernel<double, 2>), dim3(nb), dim3(256), 0, st, a);
-        else hipLaunchKernelGGL((gemv_kernel<double, 1>), dim3(nb), dim3(256), 0, st, a);
+        if (a.vec) HS_LAUNCH_TIMED((gemv_kernel<double, 2>), dim3(nb), dim3(256), 0, st, a);
+        else HS_LAUNCH_TIMED((gemv_kernel<double, 1>), dim3(nb), dim3(256), 0, st, a);
     } else {
-        if (a.vec) hipLaunchKernelGGL((gemv_kernel<float, 4>), dim3(nb), dim3(256), 0, st, a);
-        else hipLaunchKernelGGL((gemv_kernel<float, 1>), dim3(nb), dim3(256), 0, st, a);
+        if (a.vec) HS_LAUNCH_TIMED((gemv_kernel<float, 4>), dim3(nb), dim3(256), 0, st, a);
+        else HS_LAUNCH_TIMED((gemv_kernel<float, 1>), dim3(nb), dim3(256), 0, st, a);
     }
     return hipGetLastError();
 }

@@ -26,6 +26,7 @@
 // partial plane t at the rows of the bodies it belongs to (block v + t), and
 // the back-shift kernel sums the K planes per body in the order above, in
 // FP64.  K = 1 (the systolic special case) writes the result directly.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -163,12 +164,22 @@ __global__ __launch_bounds__(256) void nbody_kernel(const T *__restrict__ bodies
     }
 }
 
+bool take_timed_launch(hipEvent_t *start, hipEvent_t *stop);   // hs_kernels.hip
+
 hipError_t launch_nbody(int f64, const void *bodies, void *out, const NbodyArgs &a, int kr, hipStream_t st) {
     const int64_t nwg = (int64_t)a.p * a.sub * a.tgroups;
     if (nwg == 0) return hipSuccess;
     const dim3 grid((unsigned)nwg), block(256);
-#define HS_NB(T, R) \
-    hipLaunchKernelGGL((nbody_kernel<T, R>), grid, block, 0, st, (const T *)bodies, (T *)out, a)
+    hipEvent_t ts, te;
+    const bool timed = take_timed_launch(&ts, &te);   // hs_profile_*: events recorded by the dispatch
+#define HS_NB(T, R)                                                                                           \
+    do {                                                                                                      \
+        if (timed)                                                                                            \
+            hipExtLaunchKernelGGL((nbody_kernel<T, R>), grid, block, 0, st, ts, te, 0, (const T *)bodies,      \
+                                  (T *)out, a);                                                               \
+        else                                                                                                  \
+            hipLaunchKernelGGL((nbody_kernel<T, R>), grid, block, 0, st, (const T *)bodies, (T *)out, a);     \
+    } while (0)
     // kr: replicas per thread, 2 (K even) or 1 (K odd)
     if (f64) {
         if (kr == 2) HS_NB(double, 2);
