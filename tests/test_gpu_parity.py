@@ -347,6 +347,22 @@ def test_split_stage_sequence(dt, case):
     assert np.array_equal(got_i, ref_i)
 
 
+@pytest.mark.parametrize("dt", ["fp8_e4m3", "fp8_e4m3_r1"])
+@pytest.mark.parametrize("case", [(256, 256, 16384, 4, 2), (512, 256, 8192, 8, 2)])
+def test_split_stage_sequence_fp8(dt, case):
+    """The FP8 forms on split stage sequences (their block scales follow
+    each workgroup's first stage): FP8 gates against the oracle, small
+    integers bit for bit."""
+    from oracle.metrics import err_elem
+    m, n, k, p, K = case
+    got, ref, A64, B64 = _gemm_case(dt, m, n, k, p, K, False, seed=1740 + m, gen=inputs.uniform)
+    assert err_row(got, ref) <= TOL[dt], (dt, case, err_row(got, ref))
+    if dt == "fp8_e4m3_r1":
+        assert err_elem(got, ref, oracle.absprod(A64, B64)) <= FP8_R1_ELEM
+    got_i, ref_i, _, _ = _gemm_case(dt, m, n, k, p, K, False, seed=1750, gen=inputs.small_int)
+    assert np.array_equal(got_i, ref_i)
+
+
 def test_many_virtual_processors():
     """p = 256 (K = 16) and p = 4096 (K = 64) on small matrices."""
     _skip_no_gpu()
