@@ -4,6 +4,8 @@ import os
 import subprocess
 import sys
 
+import pytest
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
 import bench  # noqa: E402
@@ -45,3 +47,65 @@ def test_default_schedule_per_workload(monkeypatch):
     monkeypatch.setattr(sys, "argv", ["bench.py", "--workload", "nbody", "--K", "4"])
     assert bench.parse().K == 4
     assert bench.VALU_F32_PEAK == 157.3
+
+
+def _bench_line(*args):
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py")] + list(args),
+                       stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True, timeout=600)
+    assert r.returncode == 0, r.stderr[-2000:]
+    lines = [l for l in r.stdout.splitlines() if l.startswith("{")]
+    assert len(lines) == 1, r.stdout[-2000:]
+    return json.loads(lines[0])
+
+
+def _common(d, steps, warmup, unit):
+    assert isinstance(d["metric"], str) and d["metric"]
+    assert d["value"] > 0 and d["unit"] == unit
+    assert d["n_gpus"] == 1 and d["steps"] == steps and d["warmup"] == warmup
+    assert d["ms_per_step"] > 0 and d["higher_is_better"] is True
+    assert d["scaling"] == "weak" and d["vs_baseline"] is None and d["data"] == "synthetic"
+    assert isinstance(d["config"]["workload"], str) and d["config"]["workload"]
+    r = d["roofline"]
+    assert r["bound"] in ("mfma", "hbm", "alu") and r["peak"] > 0 and r["achieved"] > 0
+    assert abs(r["frac"] - r["achieved"] / r["peak"]) < 1e-9 and 0 < r["frac"] < 1
+    assert "traffic" in r
+    c = d["cpu_baseline"]
+    assert c["kind"] == "oracle" and c["value"] > 0 and c["cores"] >= 1 and c["sample"]
+
+
+@pytest.mark.gpu
+def test_bench_line_contract_step():
+    """The default step's JSON line at a small size: every contract field,
+    the roofline fraction consistent, every form's timed result checked."""
+    if not _gpu():
+        pytest.skip("no GPU")
+    d = _bench_line("--n", "1024", "--p", "8", "--steps", "2", "--warmup", "1", "--cpu-seconds", "0.5")
+    _common(d, 2, 1, "TFLOP/s")
+    assert d["dtype"] == "split3_bf16" and d["config"]["form"] == "split3_bf16"
+    assert set(d["comparison"]) == {"f32", "split2_f16"}
+    for form in ("split3_bf16", "f32", "split2_f16"):
+        a = d["accuracy"][form]
+        for out in ("C", "dA", "dB"):
+            assert a[out]["err_row"] <= 1e-5 and a[out]["err_term_u"] <= 16, (form, out, a[out])
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("args,unit,steps", [
+    (("--workload", "gemv", "--n", "2048", "--K", "8"), "GB/s", 200),
+    (("--workload", "nbody", "--bodies", "4096"), "Ginteractions/s", 10),
+    (("--workload", "complex", "--n", "512", "--p", "8"), "TFLOP/s", 10),
+])
+def test_bench_line_contract_workloads(args, unit, steps):
+    if not _gpu():
+        pytest.skip("no GPU")
+    d = _bench_line(*(args + ("--cpu-seconds", "0.5")))
+    _common(d, steps, 3, unit)
+    assert d["accuracy"]
+
+
+def _gpu():
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False
