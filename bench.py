@@ -62,7 +62,8 @@ def parse():
     ap.add_argument("--workload", default="step", choices=["step", "gemv", "complex", "nbody"],
                     help="step: the fwd+bwd product step (default); gemv: y = A.x alone "
                          "(A n x n FP32, HBM-bound; reports GB/s); complex: C = A.B on n x n "
-                         "complex64 N(0,1) data (--form c32_split3_bf16 or c32, compared with c32); "
+                         "complex64 N(0,1) data (--form c32_split3_bf16, c32 or c32_split2_f16, compared with "
+                         "the other two); "
                          "nbody: the all-pairs gravitational interaction of --bodies Plummer "
                          "bodies (FP32, ALU-bound; p = 64, K = 8 unless given)")
     ap.add_argument("--bodies", type=int, default=1 << 18, help="bodies of the nbody workload")
@@ -395,14 +396,25 @@ def complex_main(args):
         return wall, ms / max(launches, 1), launches, outs[0]
 
     useful = 3 * 8.0 * n ** 3                      # per step
+    base = {"c32": "f32", "c32_split3_bf16": "split3_bf16", "c32_split2_f16": "split2_f16"}
+
+    def mfma_frac(fm, avg_ms):
+        # one real product of 4 n^3 multiply-adds per complex product, times the form's MFMA products
+        b = base[fm]
+        return MFMA_PRODUCTS[b] * 8.0 * n ** 3 / (avg_ms * 1e-3) / 1e12 / PEAK[MFMA_PEAK_KEY[b]]
+
     wall, avg, launches_c, C_last = timed(form, args.steps, args.warmup)
-    mfma = (6 if form == "c32_split3_bf16" else 1) * 8.0 * n ** 3 * 3 * args.steps   # all timed launches
-    peak = PEAK["bf16" if form == "c32_split3_bf16" else "f32"]
-    achieved = mfma / (avg * launches_c * 1e-3) / 1e12
+    peak = PEAK[MFMA_PEAK_KEY[base[form]]]
+    achieved = mfma_frac(form, avg) * peak
     comparison = None
-    if args.compare and form != "c32":
-        w2, a2, _, _ = timed("c32", max(2, args.steps // 2), 1)
-        comparison = {"c32": {"value": useful * max(2, args.steps // 2) / w2 / 1e12, "avg_main_kernel_ms": a2}}
+    compares = [c for c in ("c32", "c32_split2_f16") if c != form] if args.compare else []
+    s2 = max(2, args.steps // 2)
+    outs_cmp = {}
+    for cf in compares:
+        w2, a2, _, outs_cmp[cf] = timed(cf, s2, 1)
+        comparison = comparison or {}
+        comparison[cf] = {"value": useful * s2 / w2 / 1e12, "avg_main_kernel_ms": a2,
+                          "mfma_frac": mfma_frac(cf, a2)}
     cpu = None
     if args.cpu_seconds > 0:
         import oracle
@@ -420,13 +432,15 @@ def complex_main(args):
         cpu = {"value": 8.0 * nrows * n * n / dt / 1e12, "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
                "sample": "%d sampled rows of C (n=%d complex, FP64 parts, %.1f s)" % (nrows, n, dt)}
         from oracle.metrics import err_elem, err_row, err_term
-        got = C_last.index_select(0, torch.as_tensor(rows, device=C_last.device)).cpu().numpy().astype(np.complex128)
         ne = min(16, nrows)
-        acc = {form: {"C": {"err_row": err_row(got, ref),
-                            "err_elem": err_elem(got[:ne], ref[:ne], oracle.complex_absprod_rows(Ah, Bh, rows[:ne])),
-                            "err_term_u": err_term(got[:ne], ref[:ne], oracle.complex_sqprod(Ah[rows[:ne]], Bh),
-                                                   2 * n) / 2.0 ** -24},
-                      "rows": "%d sampled rows of the last timed C (err_elem on %d)" % (nrows, ne)}}
+        absp = oracle.complex_absprod_rows(Ah, Bh, rows[:ne])
+        sqp = oracle.complex_sqprod(Ah[rows[:ne]], Bh)
+        acc = {}
+        for fm, Cl in [(form, C_last)] + list(outs_cmp.items()):
+            got = Cl.index_select(0, torch.as_tensor(rows, device=Cl.device)).cpu().numpy().astype(np.complex128)
+            acc[fm] = {"C": {"err_row": err_row(got, ref), "err_elem": err_elem(got[:ne], ref[:ne], absp),
+                             "err_term_u": err_term(got[:ne], ref[:ne], sqp, 2 * n) / 2.0 ** -24},
+                       "rows": "%d sampled rows of the last timed C (err_elem on %d)" % (nrows, ne)}
     else:
         acc = None
     print(json.dumps({

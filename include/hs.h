@@ -107,6 +107,11 @@ extern "C" {
  *                  result scaled back by 2^-(e_row + e_col).  FP32-level
  *                  accuracy with half the MFMA work of HS_SPLIT3_BF16.
  *                  hs_gemm, hs_gemm_tn and hs_gemm_backward.
+ *  HS_C32_SPLIT2_F16  HS_C32 with the arithmetic of HS_SPLIT2_F16 (the row
+ *                  scales are those of the real operands of the embedding:
+ *                  a 2 x 2 block's two rows share the scale of the complex
+ *                  column or row they come from).  hs_gemm, hs_gemm_tn and
+ *                  hs_gemm_backward.
  *
  * The entry points take the dtype (and hs_workspace_size its op) as a plain
  * int, so that any value a caller passes is well defined: one that is not
@@ -121,7 +126,8 @@ typedef enum {
     HS_FP8_E4M3_R1 = 6,
     HS_C32 = 7,
     HS_C32_SPLIT3_BF16 = 8,
-    HS_SPLIT2_F16 = 9
+    HS_SPLIT2_F16 = 9,
+    HS_C32_SPLIT2_F16 = 10
 } hs_dtype;
 
 typedef enum {

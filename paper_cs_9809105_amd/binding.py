@@ -13,10 +13,11 @@ LIB_PATH = os.path.join(HERE, "libhs.so")
 
 # hs_dtype
 (HS_F64, HS_F32, HS_BF16, HS_F16, HS_SPLIT3_BF16, HS_FP8_E4M3, HS_FP8_E4M3_R1,
- HS_C32, HS_C32_SPLIT3_BF16, HS_SPLIT2_F16) = range(10)
+ HS_C32, HS_C32_SPLIT3_BF16, HS_SPLIT2_F16, HS_C32_SPLIT2_F16) = range(11)
 DTYPES = {"f64": HS_F64, "f32": HS_F32, "bf16": HS_BF16, "f16": HS_F16,
           "split3_bf16": HS_SPLIT3_BF16, "fp8_e4m3": HS_FP8_E4M3, "fp8_e4m3_r1": HS_FP8_E4M3_R1,
-          "c32": HS_C32, "c32_split3_bf16": HS_C32_SPLIT3_BF16, "split2_f16": HS_SPLIT2_F16}
+          "c32": HS_C32, "c32_split3_bf16": HS_C32_SPLIT3_BF16, "split2_f16": HS_SPLIT2_F16,
+          "c32_split2_f16": HS_C32_SPLIT2_F16}
 # hs_status
 (HS_OK, HS_ERR_INVALID_VALUE, HS_ERR_NOT_SUPPORTED, HS_ERR_WORKSPACE_TOO_SMALL, HS_ERR_LAUNCH_FAILED,
  HS_ERR_EXCEEDS_SCRATCH) = range(6)
@@ -133,11 +134,12 @@ def _torch():
 
 IN_TYPES = {HS_F64: "float64", HS_F32: "float32", HS_BF16: "bfloat16", HS_F16: "float16",
             HS_SPLIT3_BF16: "float32", HS_FP8_E4M3: "float32", HS_FP8_E4M3_R1: "float32",
-            HS_C32: "complex64", HS_C32_SPLIT3_BF16: "complex64", HS_SPLIT2_F16: "float32"}
+            HS_C32: "complex64", HS_C32_SPLIT3_BF16: "complex64", HS_SPLIT2_F16: "float32",
+            HS_C32_SPLIT2_F16: "complex64"}
 
 
 def _out_type(dt):
-    if dt in (HS_C32, HS_C32_SPLIT3_BF16):
+    if dt in (HS_C32, HS_C32_SPLIT3_BF16, HS_C32_SPLIT2_F16):
         return "complex64"
     return "float64" if dt == HS_F64 else "float32"
 

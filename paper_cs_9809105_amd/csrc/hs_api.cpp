@@ -65,6 +65,7 @@ bool form_info(int dt, FormInfo *f) {
 bool complex_base(int dt, hs_dtype *base) {
     if (dt == HS_C32) { *base = HS_F32; return true; }
     if (dt == HS_C32_SPLIT3_BF16) { *base = HS_SPLIT3_BF16; return true; }
+    if (dt == HS_C32_SPLIT2_F16) { *base = HS_SPLIT2_F16; return true; }
     return false;
 }
 
@@ -293,8 +294,8 @@ hs_status run_product(const Plan &P, const Operand &X, const Operand &Y, void *o
             return HS_ERR_LAUNCH_FAILED;
     }
     if (P.f.pack == PK_SPLIT2F16) {   // row amaxes of both operands (their scales)
-        RowAmaxArgs xa{(const float *)X.ptr, X.ld, X.kmajor, P.M, P.Kd, (uint32_t *)ea};
-        RowAmaxArgs xb{(const float *)Y.ptr, Y.ld, Y.kmajor, P.N, P.Kd, (uint32_t *)eb};
+        RowAmaxArgs xa{(const float *)X.ptr, X.ld, X.kmajor, P.M, P.Kd, (uint32_t *)ea, X.embed};
+        RowAmaxArgs xb{(const float *)Y.ptr, Y.ld, Y.kmajor, P.N, P.Kd, (uint32_t *)eb, Y.embed};
         if (launch_row_amax(xa, stream) != hipSuccess || launch_row_amax(xb, stream) != hipSuccess)
             return HS_ERR_LAUNCH_FAILED;
     }

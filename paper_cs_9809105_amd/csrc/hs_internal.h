@@ -37,12 +37,19 @@ enum PackKind : int {
 // scale 2^e_r, e_r = the largest integer with amax_r 2^e_r < 2^15, found
 // from the row's amax (kept as its float bits, which order like unsigned
 // integers for amax >= 0): e_r = 15 - frexp_exp(amax_r) (15 for amax 0).
+// Complex sources (embed, see PackEmbed) are scanned as their float view
+// (ld in floats): EMB_NONE reads the operand itself; EMB_BLOCKS_H (K-major)
+// takes row r from float row r / 2 of the Kd floats of a complex row;
+// EMB_BLOCKS (MN-major, Kd / 2 rows of R floats) folds float column c into
+// rows c & ~1 and c | 1; EMB_TRANS and EMB_CONJ (MN-major, Kd / 2 rows of
+// 2R floats) fold float column c into row c / 2.
 struct RowAmaxArgs {
     const float *src;
     int64_t ld;
     int kmajor;               // 1: row r is contiguous along the contraction
     int64_t R, Kd;
     uint32_t *amax;           // [R] float bits of max |x| over the row
+    int embed;
 };
 
 // FP8 scale tiles: 128 x 128 blocks of the logical operand (rows x

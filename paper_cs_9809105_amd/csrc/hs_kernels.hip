@@ -279,7 +279,7 @@ __global__ __launch_bounds__(256) void row_amax_k_kernel(RowAmaxArgs a) {
     const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (row >= a.R) return;
-    const float *q = a.src + row * a.ld;
+    const float *q = a.src + (a.embed == EMB_BLOCKS_H ? row >> 1 : row) * a.ld;
     float m = 0.f;
     int64_t k = 0;
     if (VEC) {
@@ -297,24 +297,40 @@ __global__ __launch_bounds__(256) void row_amax_k_kernel(RowAmaxArgs a) {
     if (lane == 0) a.amax[row] = __float_as_uint(m);
 }
 
-// Row amax, MN-major source (element (kk, r) at src[kk ld + r]): thread
-// columns (4 per thread when VEC) over a slab of 256 contraction rows, then
-// one atomic max per column; the host zero-fills amax first.  Workgroup b
-// takes column block b % ncb of slab b / ncb.
+// Row amax, MN-major source (element (kk, c) of the float view at
+// src[kk ld + c]): thread columns (4 per thread when VEC) over a slab of
+// 256 contraction rows, then one atomic max per column into its row (two
+// for EMB_BLOCKS); the host zero-fills amax first.  Workgroup b takes column
+// block b % ncb of slab b / ncb.
+DEVI void amax_into_rows(const RowAmaxArgs &a, int64_t c, float m) {
+    const uint32_t bits = __float_as_uint(m);
+    if (a.embed == EMB_BLOCKS) {
+        atomicMax(a.amax + (c & ~(int64_t)1), bits);
+        atomicMax(a.amax + (c | 1), bits);
+    } else if (a.embed == EMB_TRANS || a.embed == EMB_CONJ) {
+        atomicMax(a.amax + (c >> 1), bits);
+    } else {
+        atomicMax(a.amax + c, bits);
+    }
+}
+
 template <int VEC>
 __global__ __launch_bounds__(256) void row_amax_mn_kernel(RowAmaxArgs a) {
     constexpr int CW = VEC ? 4 : 1;
-    const int64_t ncb = (a.R + 256 * CW - 1) / (256 * CW);
+    // the float view's columns and contraction rows
+    const int64_t ncol = (a.embed == EMB_TRANS || a.embed == EMB_CONJ) ? 2 * a.R : a.R;
+    const int64_t nk = a.embed == EMB_NONE ? a.Kd : a.Kd / 2;
+    const int64_t ncb = (ncol + 256 * CW - 1) / (256 * CW);
     const int64_t r0 = ((int64_t)(blockIdx.x % ncb) * 256 + threadIdx.x) * CW;
-    if (r0 >= a.R) return;
+    if (r0 >= ncol) return;
     const int64_t k0 = (int64_t)(blockIdx.x / ncb) * 256;
-    const int64_t k1 = k0 + 256 < a.Kd ? k0 + 256 : a.Kd;
+    const int64_t k1 = k0 + 256 < nk ? k0 + 256 : nk;
     float m[CW];
 #pragma unroll
     for (int j = 0; j < CW; ++j) m[j] = 0.f;
     bool done = false;
     if constexpr (VEC) {
-        if (r0 + 3 < a.R) {
+        if (r0 + 3 < ncol) {
 #pragma unroll 4
             for (int64_t kk = k0; kk < k1; ++kk) {
                 const float4 v = *(const float4 *)(a.src + kk * a.ld + r0);
@@ -330,11 +346,11 @@ __global__ __launch_bounds__(256) void row_amax_mn_kernel(RowAmaxArgs a) {
         for (int64_t kk = k0; kk < k1; ++kk)
 #pragma unroll
             for (int j = 0; j < CW; ++j)
-                if (r0 + j < a.R) m[j] = fmaxf(m[j], fabsf(a.src[kk * a.ld + r0 + j]));
+                if (r0 + j < ncol) m[j] = fmaxf(m[j], fabsf(a.src[kk * a.ld + r0 + j]));
     }
 #pragma unroll
     for (int j = 0; j < CW; ++j)
-        if (r0 + j < a.R) atomicMax(a.amax + r0 + j, __float_as_uint(m[j]));
+        if (r0 + j < ncol) amax_into_rows(a, r0 + j, m[j]);
 }
 
 // An MN-major unit of pack_kernel's numbering: row rr of group grp, block
@@ -519,7 +535,7 @@ __global__ __launch_bounds__(256) void pack_kernel(PackArgs a) {
             const bool ok = rvalid && kin < g.S_k && kk < g.Kd;
             int64_t idx = KMAJOR ? row * a.ld + kk : kk * a.ld + row;
             bool neg = false;
-            if constexpr (KIND == PK_F32 || KIND == PK_SPLIT3) {
+            if constexpr (KIND == PK_F32 || KIND == PK_SPLIT3 || KIND == PK_SPLIT2F16) {
                 // complex sources: sr = kk % 2 and c = row % 2 pick the entry
                 // of the 2 x 2 block [[re, im], [-im, re]]
                 const int64_t sr = kk & 1, c = row & 1;
@@ -1459,10 +1475,12 @@ hipError_t launch_row_amax(const RowAmaxArgs &a, hipStream_t st) {
     }
     hipError_t e = launch_fill_zero(0, a.amax, 1, a.R, a.R, st);   // zero bits = 0.0f
     if (e != hipSuccess || a.Kd == 0) return e;
-    // R Kd < 2^34 (the packing limit), so blocks < 2^18
-    const int64_t slabs = (a.Kd + 255) / 256;
-    if (vec) hipLaunchKernelGGL(row_amax_mn_kernel<1>, dim3((unsigned)((a.R + 1023) / 1024 * slabs)), dim3(256), 0, st, a);
-    else hipLaunchKernelGGL(row_amax_mn_kernel<0>, dim3((unsigned)((a.R + 255) / 256 * slabs)), dim3(256), 0, st, a);
+    // the float view (see RowAmaxArgs); R Kd < 2^34 (the packing limit), so blocks < 2^19
+    const int64_t ncol = (a.embed == EMB_TRANS || a.embed == EMB_CONJ) ? 2 * a.R : a.R;
+    const int64_t nk = a.embed == EMB_NONE ? a.Kd : a.Kd / 2;
+    const int64_t slabs = (nk + 255) / 256;
+    if (vec) hipLaunchKernelGGL(row_amax_mn_kernel<1>, dim3((unsigned)((ncol + 1023) / 1024 * slabs)), dim3(256), 0, st, a);
+    else hipLaunchKernelGGL(row_amax_mn_kernel<0>, dim3((unsigned)((ncol + 255) / 256 * slabs)), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 

@@ -48,7 +48,7 @@ def poisoned(shape, dtype, device="cuda"):
 # ---------------------------------------------------------------------------
 # err_row (relative 2-norm per row): the stated tolerances of each form
 ROW_TOL = {"f64": 1e-12, "f32": 1e-5, "split3_bf16": 1e-5, "split2_f16": 1e-5, "bf16": 1.5e-2, "f16": 3e-3,
-           "fp8_e4m3": 1e-1, "fp8_e4m3_r1": 1e-2, "c32": 1e-5, "c32_split3_bf16": 1e-5}
+           "fp8_e4m3": 1e-1, "fp8_e4m3_r1": 1e-2, "c32": 1e-5, "c32_split3_bf16": 1e-5, "c32_split2_f16": 1e-5}
 # err_term (element error over u sqrt(k sum_t (a_t b_t)^2), the statistical
 # scale of a dot product's rounding errors) for the FP32-accurate and FP64
 # forms: 16 u.  Round-to-nearest FP32 accumulation of the workloads' inputs
@@ -82,7 +82,7 @@ ELEM_C = {"f64": (3, 0), "f32": (3, 0), "bf16": (3, 0), "f16": (3, 0), "split3_b
           "split2_f16": (7, 13)}
 UNIT = {"f64": 2.0 ** -53, "f32": 2.0 ** -24, "bf16": 2.0 ** -24, "f16": 2.0 ** -24, "split3_bf16": 2.0 ** -24,
         "split2_f16": 2.0 ** -24}
-COMPLEX_BASE = {"c32": "f32", "c32_split3_bf16": "split3_bf16"}
+COMPLEX_BASE = {"c32": "f32", "c32_split3_bf16": "split3_bf16", "c32_split2_f16": "split2_f16"}
 
 
 def _base(dt, k):

@@ -246,7 +246,7 @@ def test_profile_end_without_begin():
 def test_complex_forms_argument_checks():
     L = B.lib()
     s = B.hs_schedule(2, 0)
-    for dt in (B.HS_C32, B.HS_C32_SPLIT3_BF16):
+    for dt in (B.HS_C32, B.HS_C32_SPLIT3_BF16, B.HS_C32_SPLIT2_F16):
         # transposed product: checks in complex elements, before any launch
         tn = [8, 8, 8, dt, s, FAKE, 8, FAKE, 8, FAKE, 8, FAKE, 1 << 30, None]
         bad = list(tn)
@@ -269,6 +269,7 @@ def test_complex_forms_argument_checks():
     # matrix-vector: complex64 in FP32 arithmetic only
     gv = [8, 8, B.HS_C32, s, FAKE, 8, FAKE, FAKE, None, 0, None]
     assert L.hs_gemv(8, 8, B.HS_C32_SPLIT3_BF16, s, FAKE, 8, FAKE, FAKE, None, 0, None) == B.HS_ERR_NOT_SUPPORTED
+    assert L.hs_gemv(8, 8, B.HS_C32_SPLIT2_F16, s, FAKE, 8, FAKE, FAKE, None, 0, None) == B.HS_ERR_NOT_SUPPORTED
     bad = list(gv)
     bad[4] = FAKE + 4                          # A not 8-byte aligned
     assert L.hs_gemv(*bad) == B.HS_ERR_INVALID_VALUE
@@ -288,6 +289,8 @@ def test_complex_workspace_is_that_of_the_real_embedding():
         assert ws(B.HS_OP_GEMM, m, n, k, "c32", p, K) == ws(B.HS_OP_GEMM, m, 2 * n, 2 * k, "f32", p, K)
         assert ws(B.HS_OP_GEMM, m, n, k, "c32_split3_bf16", p, K) == \
             ws(B.HS_OP_GEMM, m, 2 * n, 2 * k, "split3_bf16", p, K)
+        assert ws(B.HS_OP_GEMM, m, n, k, "c32_split2_f16", p, K) == \
+            ws(B.HS_OP_GEMM, m, 2 * n, 2 * k, "split2_f16", p, K)
         assert ws(B.HS_OP_GEMM_TN, m, n, k, "c32", p, K) == ws(B.HS_OP_GEMM_TN, m, 2 * n, 2 * k, "f32", p, K)
         # backward: dA = G . B^H (m x 2k reals, contraction 2n), dB = A^H . G (k x 2n, contraction 2m)
         assert ws(B.HS_OP_BACKWARD, m, n, k, "c32", p, K) == max(ws(B.HS_OP_GEMM, m, 2 * k, 2 * n, "f32", p, K),

@@ -696,7 +696,7 @@ def test_fp8_quantisation_bit_exact_backward(dt):
 # Complex data (the complex workload of Sec. 7): hs_gemm on complex64, run as
 # one real product of A (m x 2k) and the 2 x 2 block embedding of B.
 # ---------------------------------------------------------------------------
-CPLX = ["c32", "c32_split3_bf16"]
+CPLX = ["c32", "c32_split3_bf16", "c32_split2_f16"]
 CPLX_CASES = [(64, 48, 80, 4, 2), (77, 45, 333, 5, 1), (256, 200, 320, 8, 0), (512, 384, 640, 16, 4),
               (130, 260, 90, 3, 3), (1, 1, 1, 1, 1)]
 
@@ -795,17 +795,70 @@ def test_complex_gemv_empty_contraction():
     assert torch.equal(y.cpu(), torch.zeros(5, dtype=torch.complex64))
 
 
-def test_complex_strided_views():
+@pytest.mark.parametrize("dt", ["c32_split3_bf16", "c32_split2_f16"])
+def test_complex_strided_views(dt):
     _skip_no_gpu()
     Abig, Ahb = _cplx_dev((100, 150), 980)
     Bbig, Bhb = _cplx_dev((130, 90), 982)
     A, B = Abig[:, 10:130], Bbig[5:125, :70]        # row strides 150 and 90 complex elements
-    note("complex views")
-    C = hs.hs_gemm(A, B, dtype="c32_split3_bf16", p=6, K=2)
+    note("complex views", dt)
+    C = hs.hs_gemm(A, B, dtype=dt, p=6, K=2)
     torch.cuda.synchronize()
     ref = oracle.complex_gemm(Ahb[:, 10:130], Bhb[5:125, :70])
-    check(C.cpu().numpy().astype(np.complex128), ref, "c32_split3_bf16", Ahb[:, 10:130], Bhb[5:125, :70],
+    check(C.cpu().numpy().astype(np.complex128), ref, dt, Ahb[:, 10:130], Bhb[5:125, :70],
           what="complex views")
+
+
+def _c_split2_value(Z, axis):
+    """What each element of complex Z stands for in the complex two-piece
+    FP16 form: re and im split as in oracle.precision, with one scale per
+    row (axis 0) or column (axis 1) from the largest |re| or |im| in it."""
+    from oracle import precision as P
+    Zr = Z if axis == 0 else Z.T
+    out = np.empty_like(Zr)
+    for r in range(Zr.shape[0]):
+        e = P.row_exponent(max(np.max(np.abs(Zr[r].real)), np.max(np.abs(Zr[r].imag))))
+
+        def v(x):
+            xs = x * 2.0 ** e
+            a0 = P.f16(xs)
+            return (a0 + P.f16(xs - a0)) * 2.0 ** -e
+        out[r] = v(Zr[r].real) + 1j * v(Zr[r].imag)
+    return out if axis == 0 else out.T
+
+
+@pytest.mark.parametrize("p", [4, 3])
+def test_complex_split2_pieces_bit_exact(p):
+    """Every embedding of the complex two-piece FP16 form against the pieces
+    and scales oracle.precision assigns, bit for bit, through diagonals of
+    signed powers of two (one nonzero product per output element): A.D
+    (rows of A scaled), D.B (columns of B), At^T.D (columns of At), and the
+    backward pair with G = D: dA = D.B^H (rows of B), dB = A^H.D (columns
+    of A)."""
+    _skip_no_gpu()
+    dt = "c32_split2_f16"
+    n, k = 120, 96
+    g = np.random.default_rng(990 + p)
+    d = g.choice([-1.0, 1.0], n) * 2.0 ** g.integers(-6, 7, n)
+    dk = d[:k]
+    Dn = torch.from_numpy(np.diag(d).astype(np.complex64)).cuda()
+    Dk = torch.from_numpy(np.diag(dk).astype(np.complex64)).cuda()
+    A, Ah = _cplx_dev((n, k), 991, inputs.row_scaled)         # A n x k
+    B, Bh = _cplx_dev((k, n), 993, inputs.row_scaled)         # B k x n
+    B2, B2h = _cplx_dev((n, k), 995, inputs.row_scaled)       # travelling side of Dn . B2
+    At, Ath = _cplx_dev((n, k), 997, inputs.row_scaled)       # At^T . Dn
+    note("complex split2 pieces p=%d" % p)
+    C1 = hs.hs_gemm(A, Dk, dtype=dt, p=p, K=1)
+    C2 = hs.hs_gemm(Dn, B2, dtype=dt, p=p, K=1)
+    C3 = hs.hs_gemm_tn(At, Dn, dtype=dt, p=p, K=1)
+    dA, dB = hs.hs_gemm_backward(A, B, Dn, dtype=dt, p=p, K=1)
+    torch.cuda.synchronize()
+    host_c = lambda t: t.cpu().numpy().astype(np.complex128)
+    assert np.array_equal(host_c(C1), _c_split2_value(Ah, 0) * dk[None, :])
+    assert np.array_equal(host_c(C2), d[:, None] * _c_split2_value(B2h, 1))
+    assert np.array_equal(host_c(C3), _c_split2_value(Ath, 1).T * d[None, :])
+    assert np.array_equal(host_c(dA), d[:, None] * np.conj(_c_split2_value(Bh, 0)).T)
+    assert np.array_equal(host_c(dB), np.conj(_c_split2_value(Ah, 1)).T * d[None, :])
 
 
 def test_complex_4096_sampled_rows():
