@@ -941,7 +941,8 @@ def test_complex_backward_gaussian_integers_bit_exact(dt):
     assert np.array_equal(dB.cpu().numpy().astype(np.complex128), oracle.complex_gemm(np.conj(Ah).T, Gh))
 
 
-def test_complex_autograd():
+@pytest.mark.parametrize("dt", ["c32_split3_bf16", "c32_split2_f16"])
+def test_complex_autograd(dt):
     _skip_no_gpu()
     m, k, n = 96, 64, 80
     A, Ah = _cplx_dev((m, k), 1040)
@@ -949,11 +950,10 @@ def test_complex_autograd():
     G, Gh = _cplx_dev((m, n), 1044)
     A.requires_grad_(True)
     B.requires_grad_(True)
-    note("complex autograd")
-    C = hs_autograd.matmul(A, B, dtype="c32_split3_bf16", p=4, K=2)
+    note("complex autograd", dt)
+    C = hs_autograd.matmul(A, B, dtype=dt, p=4, K=2)
     C.backward(G)
     torch.cuda.synchronize()
-    dt = "c32_split3_bf16"
     check(C.detach().cpu().numpy().astype(np.complex128), oracle.complex_gemm(Ah, Bh), dt, Ah, Bh,
           what="complex autograd C")
     check(A.grad.cpu().numpy().astype(np.complex128), oracle.complex_gemm(Gh, np.conj(Bh).T), dt, Gh, Bh.T,

@@ -143,7 +143,7 @@ def test_random_complex(seed):
     g = inputs.rng(38000 + seed)
     m, n, k = (int(x) for x in g.integers(1, 300, size=3))
     p, K = _schedule(g)
-    dt = ["c32", "c32_split3_bf16"][seed % 2]
+    dt = ["c32", "c32_split3_bf16", "c32_split2_f16"][seed % 3]
     A, Ah = _cplx((m, k), 39000 + seed)
     At, Ath = _cplx((k, m), 40000 + seed)
     Bm, Bh = _cplx((k, n), 41000 + seed)
