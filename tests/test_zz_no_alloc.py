@@ -45,6 +45,24 @@ def test_noalloc_equals_gemm_two_calls(dt):
             check(got.cpu().double().numpy(), oracle.gemm(A64, B64), dt, A64, B64, what="noalloc %d" % i)
 
 
+@pytest.mark.parametrize("dt", ["split3_bf16", "split2_f16", "f32"])
+def test_noalloc_split_stage_sequence(dt):
+    """A long contraction on few output tiles (its stage sequence split over
+    workgroups, their planes in the scratch array), then a small product:
+    both equal to hs_gemm."""
+    _skip_no_gpu()
+    for i, (m, n, k, p, K) in enumerate([(256, 256, 16384, 4, 2), (96, 80, 200, 4, 1)]):
+        A, A64 = to_dev(inputs.normal((m, k), seed=1540 + i), dt)
+        Bm, B64 = to_dev(inputs.normal((k, n), seed=1545 + i), dt)
+        assert 0 < B.hs_workspace_size(B.HS_OP_GEMM, m, n, k, dt, p, K) <= B.HS_NOALLOC_SCRATCH_BYTES
+        note("noalloc split", dt, (m, n, k), (p, K), "call", i)
+        ref = hs.hs_gemm(A, Bm, dtype=dt, p=p, K=K, out=poisoned((m, n), torch.float32))
+        got = hs.hs_gemm_noalloc(A, Bm, poisoned((m, n), torch.float32), dtype=dt, p=p, K=K)
+        torch.cuda.synchronize()
+        assert torch.equal(got, ref), (dt, i)
+        check(got.cpu().double().numpy(), oracle.gemm(A64, B64), dt, A64, B64, what="noalloc split %d" % i)
+
+
 def test_noalloc_on_a_stream_in_a_row():
     """Back-to-back calls on one side stream (ordered by the stream), each
     equal to hs_gemm."""
