@@ -407,7 +407,7 @@ def complex_main(args):
     peak = PEAK[MFMA_PEAK_KEY[base[form]]]
     achieved = mfma_frac(form, avg) * peak
     comparison = None
-    compares = [c for c in ("c32", "c32_split2_f16") if c != form] if args.compare else []
+    compares = [c for c in ("c32", "c32_split2_f16", "c32_split3_bf16") if c != form] if args.compare else []
     s2 = max(2, args.steps // 2)
     outs_cmp = {}
     for cf in compares:
