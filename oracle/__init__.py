@@ -10,9 +10,10 @@ k, plus the transposed product, the matrix-vector product and the gradient of
 L = sum(C * G), and the complex product (``complex_gemm``, by its real
 and imaginary parts).  ``nbody`` is the all-pairs gravitational sum, the
 prototype n^2-problem (Sec. 2.2) of the two-array recipe (Sec. 4.1).  See
-``hs_oracle.c``.  ``ring`` holds a literal simulator of
-Algorithms SYSTOLIC and HYPER-SYSTOLIC (Sec. 5) and ``bases`` the regular
-hyper-systolic bases (Sec. 4.4, Sec. 5.2.1); both pin the schedule.
+``hs_oracle.c``.  ``ring`` holds a ring simulator of the systolic and
+hyper-systolic products (Sec. 5), driven by the three bases and the circular
+shift alone, and ``bases`` the regular hyper-systolic bases (Sec. 4.4,
+Sec. 5.2.1); both pin the schedule.
 
 Parity pins: see tests/test_oracle.py (identity, permutation, small-integer
 exactness, explicit transpose, associativity, central differences, exactly
