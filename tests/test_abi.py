@@ -428,3 +428,36 @@ def test_split_planes_in_workspace():
     assert ws(B.HS_OP_GEMM, 256, 256, 1024, "f32", 4, 2) == 2 * 2 ** 20
     # 1024 output tiles (n = 8192): no split, operands only
     assert ws(B.HS_OP_GEMM, 8192, 8192, 8192, "f32", 64, 2) == 2 * 8192 * 8192 * 4
+
+
+def test_header_is_plain_c(tmp_path):
+    """include/hs.h compiles as C99 and as C++ with every warning an error,
+    and a C caller can name every declared entry point, type and constant
+    (a C ABI: no C++ in the signatures)."""
+    import subprocess
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    src = tmp_path / "use_hs.c"
+    src.write_text(
+        '#include "hs.h"\n'
+        "int use(void) {\n"
+        "    hs_schedule s = {64, 2};\n"
+        "    hs_schedule r;\n"
+        "    int32_t table[8];\n"
+        "    size_t ws = hs_workspace_size(HS_OP_GEMM, 8, 8, 8, HS_SPLIT2_F16, s);\n"
+        "    hs_status st = hs_schedule_resolve(s, &r);\n"
+        "    (void)hs_schedule_table(s, table, 8);\n"
+        "    (void)hs_status_string(st);\n"
+        "    (void)hs_gemm(8, 8, 8, HS_F32, s, 0, 8, 0, 8, 0, 8, 0, 0, 0);\n"
+        "    (void)hs_gemm_tn(8, 8, 8, HS_C32_SPLIT2_F16, s, 0, 8, 0, 8, 0, 8, 0, 0, 0);\n"
+        "    (void)hs_gemv(8, 8, HS_F64, s, 0, 8, 0, 0, 0, 0, 0);\n"
+        "    (void)hs_gemm_backward(8, 8, 8, HS_SPLIT3_BF16, s, 0, 8, 0, 8, 0, 8, 0, 8, 0, 8, 0, 0, 0);\n"
+        "    (void)hs_nbody(8, HS_F32, s, 0, 0.0, 0, 0, 0, 0);\n"
+        "    (void)hs_gemm_noalloc(8, 8, 8, HS_FP8_E4M3_R1, s, 0, 8, 0, 8, 0, 8, 0);\n"
+        "    (void)hs_profile_begin();\n"
+        "    return (int)ws + (int)HS_NOALLOC_SCRATCH_BYTES + HS_ERR_EXCEEDS_SCRATCH;\n"
+        "}\n")
+    for cmd in (["gcc", "-std=c99", "-Wall", "-Wextra", "-Werror", "-pedantic", "-c"],
+                ["g++", "-std=c++17", "-Wall", "-Wextra", "-Werror", "-x", "c++", "-c"]):
+        r = subprocess.run(cmd + ["-I", inc, str(src), "-o", str(tmp_path / "use_hs.o")],
+                           stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+        assert r.returncode == 0, (cmd[0], r.stdout)
