@@ -320,7 +320,7 @@ def test_leading_dimension_views():
 SPLIT_CASES = [(256, 256, 16384, 4, 2), (300, 200, 8192, 8, 4), (512, 256, 6144, 3, 1), (64, 96, 4096, 16, 16)]
 
 
-@pytest.mark.parametrize("dt", ["f32", "split3_bf16", "split2_f16", "bf16", "f64"])
+@pytest.mark.parametrize("dt", ["f32", "split3_bf16", "split2_f16", "bf16", "f16", "f64"])
 @pytest.mark.parametrize("case", SPLIT_CASES)
 def test_split_stage_sequence(dt, case):
     """C = A.B, A^T.B and the backward pair where the stage sequence is split
