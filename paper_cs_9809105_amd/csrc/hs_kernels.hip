@@ -601,7 +601,7 @@ struct MmCfg {
     static const int LPS = UA + UB;                     // DMA loads per thread per stage
     // One wave per SIMD (4 waves of 128 x 128 on the 256 x 256 tile): both
     // operands through LDS, two slots of static LDS, the stage interleaved
-    // by hand (plain BF16 and FP16)
+    // by hand (FP32, plain BF16 and FP16)
     static const bool W1 = WAVES == 4 && BM == 256;
     // B fragments straight from memory into registers (32x32 families)
     static const bool BD = FAM != FAM_F64 && FAM != FAM_FP8 && !W1;
@@ -1113,9 +1113,14 @@ void mm_kernel(MainArgs a) {
         __syncthreads();
         read_chunk(slot0, 0, fa0, fb0);
         // sched_group_barrier masks: 0x008 MFMA, 0x020 global load, 0x100
-        // LDS read, 0x200 LDS write.  First half: MFMA, read, write, MFMA,
-        // load, eight times (16 MFMAs, 8 of each memory operation); second
-        // half: MFMA, read, MFMA, eight times.
+        // LDS read, 0x200 LDS write.  A chunk has W1_RD fragment reads (as
+        // many as the stage's loads and LDS writes) and W1_PER MFMAs per
+        // read (2 for BF16/FP16, 8 for FP32's 32x32x2).  First half, W1_RD
+        // times: MFMA, read, write, W1_PER - 1 MFMAs, load; second half,
+        // W1_RD times: MFMA, read, W1_PER - 1 MFMAs.
+        constexpr int W1_RD = C::TM + C::TN;
+        constexpr int W1_PER = C::TM * C::TN * (FAM == FAM_F32 ? 4 : 1) / W1_RD;
+        static_assert(W1_RD == C::LPS && W1_PER >= 2, "interleave pattern");
 #define HS_W1_STEP(X, Y, RLOAD, RSTORE)                                                        \
     {                                                                                          \
         fetch_offsets(ach, bch);                                                               \
@@ -1123,20 +1128,20 @@ void mm_kernel(MainArgs a) {
         read_chunk(X, 1, fa1, fb1);                                                            \
         stage_load<C::UA, C::UB>(RLOAD, rsA, rsB, a_off, b_off, ach, bch);                     \
         stage_store<C::UA, C::UB, C::A_STAGE, C::NT>(RSTORE, Y, tid);                          \
-        _Pragma("unroll") for (int i = 0; i < 8; ++i) {                                        \
+        _Pragma("unroll") for (int i = 0; i < W1_RD; ++i) {                                    \
             __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);                                 \
             __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);                                 \
             __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);                                 \
-            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);                                 \
+            __builtin_amdgcn_sched_group_barrier(0x008, W1_PER - 1, 0);                        \
             __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);                                 \
         }                                                                                      \
         __syncthreads();                                                                       \
         mfma_chunk(fa1, fb1);                                                                  \
         read_chunk(Y, 0, fa0, fb0);                                                            \
-        _Pragma("unroll") for (int i = 0; i < 8; ++i) {                                        \
+        _Pragma("unroll") for (int i = 0; i < W1_RD; ++i) {                                    \
             __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);                                 \
             __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);                                 \
-            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);                                 \
+            __builtin_amdgcn_sched_group_barrier(0x008, W1_PER - 1, 0);                        \
         }                                                                                      \
         if (++s >= nstages) break;                                                             \
     }
@@ -1515,12 +1520,13 @@ int mm_chunks_per_stage(int fam, int form) {
     return form == 1 || form == 2 ? 1 : 2;
 }
 
-// 8 waves (2 per SIMD) for the 256 x 256 tiles, 4 (one per SIMD) for plain
-// BF16 and FP16 (measured at n = 8192: 0.930 against 0.970 ms for BF16,
-// 0.970 against 1.008 ms for FP16) and for FP64's 64 x 64.
+// 8 waves (2 per SIMD) for the split forms' and FP8's 256 x 256 tiles, 4
+// (one per SIMD) for FP32, plain BF16 and FP16 (measured at n = 8192 on
+// one box: FP32 7.33 against 7.61 ms, BF16 0.930 against 0.970 ms, FP16
+// 0.970 against 1.008 ms) and for FP64's 64 x 64.
 hipError_t launch_mm(int fam, int form, const MainArgs &a, hipStream_t st) {
     if (fam == FAM_F64) return launch_mm_t<FAM_F64, 0, 64, 64, 4, 4>(a, st);
-    if (fam == FAM_F32) return launch_mm_t<FAM_F32, 0, 256, 256, 2, 8>(a, st);
+    if (fam == FAM_F32) return launch_mm_t<FAM_F32, 0, 256, 256, 2, 4>(a, st);
     if (fam == FAM_F16 && form == 0) return launch_mm_t<FAM_F16, 0, 256, 256, 2, 4>(a, st);
     if (fam == FAM_F16 && form == 2) return launch_mm_t<FAM_F16, 2, 256, 256, 1, 8>(a, st);
     if (fam == FAM_BF16 && form == 0) return launch_mm_t<FAM_BF16, 0, 256, 256, 2, 4>(a, st);
