@@ -1075,13 +1075,14 @@ void mm_kernel(MainArgs a) {
         // stage is laid out by hand.  Each LDS slot is a static array of
         // its own, which lets the compiler place the reads of one slot
         // between the writes to the other.  The one barrier per stage sits
-        // in its middle: before it the wave multiplies chunk 0 (fragments
-        // already in registers) while it reads chunk 1, issues the loads of
-        // stage s + 2 and writes stage s + 1 (loaded a stage earlier) into
-        // the other slot; after it the wave multiplies chunk 1 while it
-        // reads chunk 0 of stage s + 1 from the other slot.  A slot is
-        // rewritten only after the barrier that follows its last read.
-        static_assert(CPS == 2, "two chunks per stage");
+        // before its last chunk: until then the wave multiplies chunk c
+        // (fragments already in registers) while it reads chunk c + 1,
+        // issues the loads of stage s + 2 and writes stage s + 1 (loaded a
+        // stage earlier) into the other slot; after it the wave multiplies
+        // the last chunk while it reads chunk 0 of stage s + 1 from the other
+        // slot.  A slot is rewritten only after the barrier that follows its
+        // last read.
+        static_assert(CPS >= 2, "at least two chunks per stage");
         __shared__ __attribute__((aligned(16))) uint8_t slot0[C::STAGE];
         __shared__ __attribute__((aligned(16))) uint8_t slot1[C::STAGE];
         u32x4 r0s[C::LPS], r1s[C::LPS];
@@ -1113,36 +1114,53 @@ void mm_kernel(MainArgs a) {
         __syncthreads();
         read_chunk(slot0, 0, fa0, fb0);
         // sched_group_barrier masks: 0x008 MFMA, 0x020 global load, 0x100
-        // LDS read, 0x200 LDS write.  A chunk has W1_RD fragment reads (as
-        // many as the stage's loads and LDS writes) and W1_PER MFMAs per
-        // read (2 for BF16/FP16, 8 for FP32's 32x32x2).  First half, W1_RD
-        // times: MFMA, read, write, W1_PER - 1 MFMAs, load; second half,
-        // W1_RD times: MFMA, read, W1_PER - 1 MFMAs.
+        // LDS read, 0x200 LDS write.  A chunk has W1_RD fragment reads and
+        // W1_PER MFMAs per read (2 for BF16/FP16, 8 for FP32's 32x32x2).
+        // Before the barrier, W1_SLOTS times: MFMA, read, (write), W1_PER - 1
+        // MFMAs, (load), the LPS loads and writes on the first slots; after
+        // it, W1_RD times: MFMA, read, W1_PER - 1 MFMAs.
         constexpr int W1_RD = C::TM + C::TN;
         constexpr int W1_PER = C::TM * C::TN * (FAM == FAM_F32 ? 4 : 1) / W1_RD;
-        static_assert(W1_RD == C::LPS && W1_PER >= 2, "interleave pattern");
+        constexpr int W1_SLOTS = (CPS - 1) * W1_RD;          // reads before the barrier
+        static_assert(C::LPS <= W1_SLOTS && W1_PER >= 2, "interleave pattern");
+        // Before the barrier: chunks 0 .. CPS-2 (each while reading the next
+        // chunk of this slot), the loads of stage s + 2 and the LDS writes of
+        // stage s + 1 into the other slot.  After it: the last chunk, while
+        // reading chunk 0 of stage s + 1 from the other slot.  Every read of
+        // this slot precedes the barrier, so the next stage may rewrite it.
+        auto first_part = [&](const uint8_t *X, uint8_t *Y, u32x4 (&RLOAD)[C::LPS], const u32x4 (&RSTORE)[C::LPS]) {
+#pragma unroll
+            for (int c = 0; c + 1 < CPS; ++c) {
+                if (c % 2 == 0) { mfma_chunk(fa0, fb0); read_chunk(X, c + 1, fa1, fb1); }
+                else { mfma_chunk(fa1, fb1); read_chunk(X, c + 1, fa0, fb0); }
+            }
+            stage_load<C::UA, C::UB>(RLOAD, rsA, rsB, a_off, b_off, ach, bch);
+            stage_store<C::UA, C::UB, C::A_STAGE, C::NT>(RSTORE, Y, tid);
+#pragma unroll
+            for (int i = 0; i < W1_SLOTS; ++i) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+                if (i < C::LPS) __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, W1_PER - 1, 0);
+                if (i < C::LPS) __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+            }
+        };
+        auto last_part = [&](const uint8_t *Y) {
+            if constexpr ((CPS - 1) % 2 == 0) { mfma_chunk(fa0, fb0); read_chunk(Y, 0, fa0, fb0); }
+            else { mfma_chunk(fa1, fb1); read_chunk(Y, 0, fa0, fb0); }
+#pragma unroll
+            for (int i = 0; i < W1_RD; ++i) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, W1_PER - 1, 0);
+            }
+        };
 #define HS_W1_STEP(X, Y, RLOAD, RSTORE)                                                        \
     {                                                                                          \
         fetch_offsets(ach, bch);                                                               \
-        mfma_chunk(fa0, fb0);                                                                  \
-        read_chunk(X, 1, fa1, fb1);                                                            \
-        stage_load<C::UA, C::UB>(RLOAD, rsA, rsB, a_off, b_off, ach, bch);                     \
-        stage_store<C::UA, C::UB, C::A_STAGE, C::NT>(RSTORE, Y, tid);                          \
-        _Pragma("unroll") for (int i = 0; i < W1_RD; ++i) {                                    \
-            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);                                 \
-            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);                                 \
-            __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);                                 \
-            __builtin_amdgcn_sched_group_barrier(0x008, W1_PER - 1, 0);                        \
-            __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);                                 \
-        }                                                                                      \
+        first_part(X, Y, RLOAD, RSTORE);                                                       \
         __syncthreads();                                                                       \
-        mfma_chunk(fa1, fb1);                                                                  \
-        read_chunk(Y, 0, fa0, fb0);                                                            \
-        _Pragma("unroll") for (int i = 0; i < W1_RD; ++i) {                                    \
-            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);                                 \
-            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);                                 \
-            __builtin_amdgcn_sched_group_barrier(0x008, W1_PER - 1, 0);                        \
-        }                                                                                      \
+        last_part(Y);                                                                          \
         if (++s >= nstages) break;                                                             \
     }
         for (int s = 0; s < nstages;) {
@@ -1516,20 +1534,22 @@ int mm_chunks_per_stage(int fam, int form) {
     if (fam == FAM_F32) return 2;
     // split forms one 16-deep chunk per stage (split-BF16: 48 MFMAs per wave;
     // two-piece FP16: 24, measured 2.45 ms against 2.60 with two chunks at
-    // n = 8192), BF16 and FP16 two
-    return form == 1 || form == 2 ? 1 : 2;
+    // n = 8192), BF16 and FP16 four (64 per wave; 0.915 against 0.934 ms for
+    // BF16 with two at n = 8192)
+    return form == 1 || form == 2 ? 1 : 4;
 }
 
 // 8 waves (2 per SIMD) for the split forms' and FP8's 256 x 256 tiles, 4
 // (one per SIMD) for FP32, plain BF16 and FP16 (measured at n = 8192 on
-// one box: FP32 7.33 against 7.61 ms, BF16 0.930 against 0.970 ms, FP16
-// 0.970 against 1.008 ms) and for FP64's 64 x 64.
+// one box against 8 waves: FP32 7.33 against 7.61 ms, BF16 0.930 against
+// 0.970 ms, FP16 0.970 against 1.008 ms, with two chunks per stage) and for
+// FP64's 64 x 64.
 hipError_t launch_mm(int fam, int form, const MainArgs &a, hipStream_t st) {
     if (fam == FAM_F64) return launch_mm_t<FAM_F64, 0, 64, 64, 4, 4>(a, st);
     if (fam == FAM_F32) return launch_mm_t<FAM_F32, 0, 256, 256, 2, 4>(a, st);
-    if (fam == FAM_F16 && form == 0) return launch_mm_t<FAM_F16, 0, 256, 256, 2, 4>(a, st);
+    if (fam == FAM_F16 && form == 0) return launch_mm_t<FAM_F16, 0, 256, 256, 4, 4>(a, st);
     if (fam == FAM_F16 && form == 2) return launch_mm_t<FAM_F16, 2, 256, 256, 1, 8>(a, st);
-    if (fam == FAM_BF16 && form == 0) return launch_mm_t<FAM_BF16, 0, 256, 256, 2, 4>(a, st);
+    if (fam == FAM_BF16 && form == 0) return launch_mm_t<FAM_BF16, 0, 256, 256, 4, 4>(a, st);
     if (fam == FAM_BF16 && form == 1) return launch_mm_t<FAM_BF16, 1, 256, 256, 1, 8>(a, st);
     if (fam == FAM_FP8 && form == 0) return launch_mm_t<FAM_FP8, 0, 256, 256, 2, 8>(a, st);
     if (fam == FAM_FP8 && form == 1) return launch_mm_t<FAM_FP8, 1, 256, 256, 1, 8>(a, st);
